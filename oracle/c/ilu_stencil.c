@@ -1,0 +1,131 @@
+/* Oracle (TEST INFRASTRUCTURE ONLY): ILU(0) and the two substitutions of the
+ * paper's one-step preconditioner application, on a matrix whose sparsity
+ * pattern NZ(M) is a fixed set of offsets clipped to the grid.
+ *
+ * Alg. 2 (ILU(0)), Alg. 3 (forward substitution, unit lower L) and Alg. 4
+ * (backward substitution, upper U), taken in the paper's order: rows in
+ * increasing index, and inside a row the lower columns k in increasing order,
+ * each followed by the update of the later columns j of the same row.
+ * Reading of Alg. 4: the inner loop runs over j = i+1..n (the printed bound
+ * would read z(i) before it is set).
+ *
+ * Storage: H[row * noff + o] is entry (row, row + offset_o); offsets are
+ * listed in column order and include (0,0,0); entries whose column falls
+ * outside the grid are never read or written. Plain C99, single thread. */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int d, n1, noff, diag;
+    const int *off;   /* noff x 3: dx, dy, dz */
+} grid_t;
+
+static void coords(const grid_t *g, int64_t row, int c[3]) {
+    c[0] = (int)(row % g->n1);
+    c[1] = g->d > 1 ? (int)((row / g->n1) % g->n1) : 0;
+    c[2] = g->d > 2 ? (int)(row / ((int64_t)g->n1 * g->n1)) : 0;
+}
+
+static int in_grid(const grid_t *g, const int c[3], int o, int64_t *col,
+                   int64_t row) {
+    const int *dd = g->off + 3 * o;
+    for (int k = 0; k < g->d; ++k) {
+        int v = c[k] + dd[k];
+        if (v < 0 || v >= g->n1) return 0;
+    }
+    int64_t n1 = g->n1;
+    *col = row + dd[0] + n1 * dd[1] + n1 * n1 * dd[2];
+    return 1;
+}
+
+/* index of offset (a - b) in the list, or -1 */
+static int find_off(const grid_t *g, const int *a, const int *b) {
+    for (int o = 0; o < g->noff; ++o) {
+        const int *dd = g->off + 3 * o;
+        if (dd[0] == a[0] - b[0] && dd[1] == a[1] - b[1] && dd[2] == a[2] - b[2])
+            return o;
+    }
+    return -1;
+}
+
+/* Alg. 2 in place on H. Returns 0, or 1 + row of the first zero pivot. */
+int64_t ilu0_stencil(int d, int n1, int noff, const int *off, double *H) {
+    grid_t g = {d, n1, noff, -1, off};
+    for (int o = 0; o < noff; ++o)
+        if (off[3 * o] == 0 && off[3 * o + 1] == 0 && off[3 * o + 2] == 0) g.diag = o;
+    if (g.diag < 0) return -1;
+    /* pair table: for offsets ok (lower) and oj (after ok in column order),
+       the offset of column j relative to row k = off[oj] - off[ok] */
+    int *pair = (int *)malloc(sizeof(int) * (size_t)noff * noff);
+    for (int ok = 0; ok < noff; ++ok)
+        for (int oj = 0; oj < noff; ++oj)
+            pair[(size_t)ok * noff + oj] = find_off(&g, off + 3 * oj, off + 3 * ok);
+    int64_t n = 1;
+    for (int k = 0; k < d; ++k) n *= n1;
+    for (int64_t i = 0; i < n; ++i) {
+        int c[3];
+        coords(&g, i, c);
+        double *Hi = H + i * noff;
+        for (int ok = 0; ok < g.diag; ++ok) {          /* k < i in NZ(i) */
+            int64_t k;
+            if (!in_grid(&g, c, ok, &k, i)) continue;
+            double *Hk = H + k * noff;
+            double pivot = Hk[g.diag];
+            if (pivot == 0.0) { free(pair); return 1 + k; }
+            Hi[ok] /= pivot;
+            double lik = Hi[ok];
+            for (int oj = ok + 1; oj < noff; ++oj) {   /* j > k in NZ(i) */
+                int64_t j;
+                if (!in_grid(&g, c, oj, &j, i)) continue;
+                int okj = pair[(size_t)ok * noff + oj];
+                if (okj < 0) continue;                  /* (k, j) not in NZ */
+                Hi[oj] -= lik * Hk[okj];
+            }
+        }
+    }
+    free(pair);
+    return 0;
+}
+
+/* Alg. 3: L y = r with L unit lower (strict part in H). */
+void forward_stencil(int d, int n1, int noff, const int *off, const double *H,
+                     const double *r, double *y) {
+    grid_t g = {d, n1, noff, -1, off};
+    for (int o = 0; o < noff; ++o)
+        if (off[3 * o] == 0 && off[3 * o + 1] == 0 && off[3 * o + 2] == 0) g.diag = o;
+    int64_t n = 1;
+    for (int k = 0; k < d; ++k) n *= n1;
+    for (int64_t i = 0; i < n; ++i) {
+        int c[3];
+        coords(&g, i, c);
+        double acc = 0.0;
+        for (int o = 0; o < g.diag; ++o) {
+            int64_t j;
+            if (!in_grid(&g, c, o, &j, i)) continue;
+            acc += H[i * noff + o] * y[j];
+        }
+        y[i] = r[i] - acc;
+    }
+}
+
+/* Alg. 4: U z = y with U upper (diagonal and upper part in H). */
+void backward_stencil(int d, int n1, int noff, const int *off, const double *H,
+                      const double *y, double *z) {
+    grid_t g = {d, n1, noff, -1, off};
+    for (int o = 0; o < noff; ++o)
+        if (off[3 * o] == 0 && off[3 * o + 1] == 0 && off[3 * o + 2] == 0) g.diag = o;
+    int64_t n = 1;
+    for (int k = 0; k < d; ++k) n *= n1;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int c[3];
+        coords(&g, i, c);
+        double acc = y[i];
+        for (int o = g.diag + 1; o < noff; ++o) {
+            int64_t j;
+            if (!in_grid(&g, c, o, &j, i)) continue;
+            acc -= H[i * noff + o] * z[j];
+        }
+        z[i] = acc / H[i * noff + g.diag];
+    }
+}
