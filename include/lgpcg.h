@@ -1,0 +1,173 @@
+/* lgpcg.h - C ABI of the MI355X (gfx950) preconditioned Legendre-Galerkin
+ * PCG solver for  -div(a grad u) + b u = f  on (-1,1)^d, u = 0 on the
+ * boundary, d = 2 or 3 (Diao, Hu, Ma, arXiv 2004.13961).
+ *
+ * Discretisation (paper Sec. 3): unknowns are the coefficients of the compact
+ * basis phi_k = L_k - L_{k+2}, k = 0..N-2, in tensor form, x index fastest:
+ * a vector has (N-1)^d doubles, entry [kx + (N-1)*(ky + (N-1)*kz)].
+ * Coefficients a, b and data f enter as values at the (N+1)^d tensor grid of
+ * Legendre-Gauss nodes (roots of L_{N+1}, Sec. 2.2), x fastest, node order
+ * ascending (see lgp_gauss_legendre). The operator K = A + B is the one of
+ * the fast matrix-vector product of Sec. 4.3: the bilinear form with I_N
+ * applied to a grad u and b u, i.e. (N+1)-point Gauss quadrature per
+ * direction.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked "device" are HIP device pointers; the others are host.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream). All
+ *     device work is enqueued on it; a call returns after enqueueing unless
+ *     its comment says it synchronises.
+ *   - The caller allocates every device byte (size queries below) and keeps
+ *     it alive until the handle that uses it is destroyed. The library never
+ *     allocates device memory. Handles are small host objects owned by the
+ *     library and released by the matching destroy call.
+ *   - Every function returns an lgp_status; nothing throws across the ABI.
+ *     After a non-OK build or factor the handle is not created.
+ *   - A handle must not be used from two host threads at once. Calls on one
+ *     handle must be ordered on a single stream.
+ */
+#ifndef LGPCG_H
+#define LGPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LGP_OK = 0,
+    LGP_E_ARG = 1,        /* bad argument: d not in {2,3}, N < 2, null pointer, T < 0 */
+    LGP_E_NOMEM = 2,      /* caller buffer smaller than the size query returned */
+    LGP_E_COEF = 3,       /* a <= 0, b < 0 or a non-finite value at a node */
+    LGP_E_ILU_PIVOT = 4,  /* ILU(0) pivot <= 0 or non-finite (Alg. 2 assumes existence) */
+    LGP_E_NOCONV = 5,     /* max_iter reached before the stop rule of Alg. 1 */
+    LGP_E_BREAKDOWN = 6,  /* p'Kp <= 0 or r'z <= 0 in PCG */
+    LGP_E_HIP = 7,        /* a HIP runtime call failed; see lgp_last_hip_error */
+    LGP_E_UNSUPPORTED = 8 /* valid request this build does not serve */
+} lgp_status;
+
+typedef enum { LGP_F64 = 0, LGP_F32 = 1, LGP_BF16 = 2 } lgp_dtype;
+
+typedef struct lgp_problem_s* lgp_problem;
+typedef struct lgp_factor_s* lgp_factor;
+
+/* ----------------------------------------------------------- utilities -- */
+int lgp_version(void);
+const char* lgp_status_str(lgp_status s);
+int lgp_last_hip_error(void);            /* last hipError_t seen, 0 if none */
+
+/* Legendre-Gauss nodes (roots of L_{N+1}, Sec. 2.2) in ascending order and
+ * their weights; x and w are host arrays of N+1 doubles. Newton iteration on
+ * the three-term recurrence of Sec. 2.1. */
+lgp_status lgp_gauss_legendre(int N, double* x, double* w);
+
+/* ------------------------------------------------------------ problem -- */
+/* Device bytes needed by lgp_build_problem for (d, N). */
+size_t lgp_problem_bytes(int d, int N);
+
+/* Build the operator K = A + B of Sec. 3 / Sec. 4.3 from nodal coefficient
+ * values a_nodes, b_nodes (device, (N+1)^d doubles each, x fastest). The
+ * model problem requires a > 0 and b >= 0 (Sec. 3): the call checks every
+ * node and returns LGP_E_COEF otherwise (it synchronises `stream` for that
+ * check). The nodal arrays are copied; buf (device, buf_bytes >=
+ * lgp_problem_bytes) holds tables, weighted coefficients and matvec
+ * scratch and must outlive the handle. */
+lgp_status lgp_build_problem(int d, int N, const double* a_nodes, const double* b_nodes,
+                             void* buf, size_t buf_bytes, void* stream, lgp_problem* out);
+void lgp_destroy_problem(lgp_problem p);
+
+/* Load vector F_k = (I_N f, psi_k) (Sec. 3 with the quadrature of Sec. 4.3):
+ * f_nodes device (N+1)^d, F device (N-1)^d. Uses the problem's scratch. */
+lgp_status lgp_load_vector(lgp_problem p, const double* f_nodes, double* F, void* stream);
+
+/* y = (A + B) u, the fast matrix-vector product of Sec. 4.3 computed by
+ * sum-factorised contractions on the matrix cores. prec = LGP_F64: u, y are
+ * double. prec = LGP_F32: u, y are float, contractions in FP32. prec =
+ * LGP_BF16: u, y are float, contraction operands rounded to bfloat16 with
+ * FP32 accumulation. u and y must not alias. Uses the problem's scratch, so
+ * matvecs on one problem must be stream-ordered. */
+lgp_status lgp_matvec(lgp_problem p, const void* u, void* y, lgp_dtype prec, void* stream);
+
+/* ------------------------------------------------------ preconditioner -- */
+/* Device bytes for the ILU(0) factors of M with truncation degrees Ta (for
+ * a) and Tb (for b); store = LGP_F32 adds single-precision copies of the
+ * factors for the inner sweeps of the mixed-precision solve. */
+size_t lgp_factor_bytes(lgp_problem p, int Ta, int Tb, lgp_dtype store);
+
+/* Preconditioner of Sec. 4.1: a and b replaced by their Legendre series
+ * truncated to indices <= Ta (resp. Tb) in each direction (coefficients =
+ * the discrete Legendre transform of the nodal values, Sec. 2.2; terms below
+ * 1e-13 of the largest are dropped), M assembled exactly (product formula,
+ * Lemma LegProduct; Kronecker form of Sec. 4.2), then ILU(0) (Alg. 2) in
+ * FP64 on the GPU over NZ(M). Because M and NZ(M) are symmetric the factor
+ * is stored as unit-lower L plus pivots D, with U = D L^T. Returns
+ * LGP_E_ILU_PIVOT if a pivot is <= 0 or non-finite. Synchronises `stream`
+ * (pattern selection and the pivot check read device results). */
+lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store,
+                        void* buf, size_t buf_bytes, void* stream, lgp_factor* out);
+void lgp_destroy_factor(lgp_factor m);
+
+/* One-step preconditioner application of Sec. 4.2: z = U^{-1} L^{-1} r
+ * (forward substitution Alg. 3, then backward substitution Alg. 4). r, z
+ * device (N-1)^d doubles; must not alias. */
+lgp_status lgp_precond_apply(lgp_factor m, const double* r, double* z, void* stream);
+/* The two halves separately: y = L^{-1} r (Alg. 3) and z = U^{-1} y (Alg. 4). */
+lgp_status lgp_ilu_forward(lgp_factor m, const double* r, double* y, void* stream);
+lgp_status lgp_ilu_backward(lgp_factor m, const double* y, double* z, void* stream);
+
+/* Layout of a factor, for inspection. offsets (host, 3*noff ints, filled by
+ * the library and valid while the handle lives) lists NZ(M) as (dx,dy,dz) in
+ * column order; the first n_lower are the strictly lower ones. L (device)
+ * is row-major [n][n_lower]: L[i*n_lower + k] = L(i, i + offset_k), zero
+ * where the column leaves the grid. D (device, n) holds the pivots U(i,i). */
+typedef struct {
+    int d, N, n1, Ta, Tb;
+    int64_t n;
+    int noff, n_lower;
+    const int* offsets;
+    const double* L;
+    const double* D;
+    int levels;          /* hyperplane depth of the sweeps */
+} lgp_factor_desc;
+lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out);
+
+/* ---------------------------------------------------------------- PCG -- */
+typedef struct {
+    double rtol;         /* stop when ||r||_2 <= rtol ||F||_2 (Alg. 1); default 1e-10 */
+    int max_iter;        /* k_max of Alg. 1; default 2000 */
+    lgp_dtype inner;     /* LGP_F64: plain PCG. LGP_F32 / LGP_BF16: FP64 iterative
+                            refinement around an inner PCG whose matvec runs in that
+                            precision and whose sweeps use FP32 factors */
+    double inner_rtol;   /* inner stop rule in mixed mode; default 1e-4 */
+    int max_outer;       /* refinement steps in mixed mode; default 60 */
+    int check_every;     /* iterations enqueued between host convergence checks; default 4 */
+} lgp_solve_opts;
+
+typedef struct {
+    int iters;               /* PCG iterations (summed over inner solves in mixed mode) */
+    int outer;               /* refinement steps (mixed) or restarts (FP64) */
+    double relres_true;      /* ||F - K x||_2 / ||F||_2 recomputed in FP64 at exit */
+    double relres_recursive; /* the recursive residual of the last PCG iteration */
+    lgp_status status;
+} lgp_solve_info;
+
+/* Device bytes of the PCG workspace for problem p and inner precision. */
+size_t lgp_solve_workspace_bytes(lgp_problem p, lgp_dtype inner);
+
+/* Solve (A + B) x = F by PCG (Alg. 1) with the one-step ILU(0)
+ * preconditioner. F device (N-1)^d; x device, in: initial guess, out:
+ * solution. Scalars stay on the device; the host reads the convergence flag
+ * every check_every iterations. After Alg. 1 stops, the true residual is
+ * recomputed in FP64; if it exceeds rtol the iteration restarts from x (at
+ * most 3 times). Synchronises `stream`; fills *info (host). opts may be
+ * NULL for the defaults. */
+lgp_status lgp_pcg_solve(lgp_problem p, lgp_factor m, const double* F, double* x,
+                         const lgp_solve_opts* opts, void* ws, size_t ws_bytes,
+                         void* stream, lgp_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LGPCG_H */

@@ -39,14 +39,25 @@ static int in_grid(const grid_t *g, const int c[3], int o, int64_t *col,
     return 1;
 }
 
-/* index of offset (a - b) in the list, or -1 */
-static int find_off(const grid_t *g, const int *a, const int *b) {
+/* lookup cube over offset differences: index of an offset in the list, -1
+   if absent; R = half-width of the cube */
+static int *offset_cube(const grid_t *g, int *R) {
+    int h = 0;
+    for (int o = 0; o < g->noff; ++o)
+        for (int k = 0; k < 3; ++k) {
+            int v = g->off[3 * o + k];
+            if (v < 0) v = -v;
+            if (v > h) h = v;
+        }
+    *R = 2 * h;
+    int W = 2 * (*R) + 1;
+    int *cube = (int *)malloc(sizeof(int) * (size_t)W * W * W);
+    for (size_t t = 0; t < (size_t)W * W * W; ++t) cube[t] = -1;
     for (int o = 0; o < g->noff; ++o) {
         const int *dd = g->off + 3 * o;
-        if (dd[0] == a[0] - b[0] && dd[1] == a[1] - b[1] && dd[2] == a[2] - b[2])
-            return o;
+        cube[((size_t)(dd[2] + *R) * W + (dd[1] + *R)) * W + (dd[0] + *R)] = o;
     }
-    return -1;
+    return cube;
 }
 
 /* Alg. 2 in place on H. Returns 0, or 1 + row of the first zero pivot. */
@@ -57,10 +68,31 @@ int64_t ilu0_stencil(int d, int n1, int noff, const int *off, double *H) {
     if (g.diag < 0) return -1;
     /* pair table: for offsets ok (lower) and oj (after ok in column order),
        the offset of column j relative to row k = off[oj] - off[ok] */
-    int *pair = (int *)malloc(sizeof(int) * (size_t)noff * noff);
+    int R;
+    int *cube = offset_cube(&g, &R);
+    int W = 2 * R + 1;
+    /* for each ok: the later offsets oj (oj > ok) with (k, j) in NZ, and the
+       offset index of column j relative to row k (CSR) */
+    int64_t *ptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(noff + 1));
+    int64_t cnt = 0;
     for (int ok = 0; ok < noff; ++ok)
-        for (int oj = 0; oj < noff; ++oj)
-            pair[(size_t)ok * noff + oj] = find_off(&g, off + 3 * oj, off + 3 * ok);
+        for (int oj = ok + 1; oj < noff; ++oj) {
+            const int *a = off + 3 * oj, *b = off + 3 * ok;
+            if (cube[((size_t)(a[2] - b[2] + R) * W + (a[1] - b[1] + R)) * W + (a[0] - b[0] + R)] >= 0) ++cnt;
+        }
+    int *pj = (int *)malloc(sizeof(int) * (size_t)(cnt + 1));
+    int *pkj = (int *)malloc(sizeof(int) * (size_t)(cnt + 1));
+    cnt = 0;
+    for (int ok = 0; ok < noff; ++ok) {
+        ptr[ok] = cnt;
+        for (int oj = ok + 1; oj < noff; ++oj) {
+            const int *a = off + 3 * oj, *b = off + 3 * ok;
+            int v = cube[((size_t)(a[2] - b[2] + R) * W + (a[1] - b[1] + R)) * W + (a[0] - b[0] + R)];
+            if (v >= 0) { pj[cnt] = oj; pkj[cnt] = v; ++cnt; }
+        }
+    }
+    ptr[noff] = cnt;
+    free(cube);
     int64_t n = 1;
     for (int k = 0; k < d; ++k) n *= n1;
     for (int64_t i = 0; i < n; ++i) {
@@ -72,19 +104,18 @@ int64_t ilu0_stencil(int d, int n1, int noff, const int *off, double *H) {
             if (!in_grid(&g, c, ok, &k, i)) continue;
             double *Hk = H + k * noff;
             double pivot = Hk[g.diag];
-            if (pivot == 0.0) { free(pair); return 1 + k; }
+            if (pivot == 0.0) { free(ptr); free(pj); free(pkj); return 1 + k; }
             Hi[ok] /= pivot;
             double lik = Hi[ok];
-            for (int oj = ok + 1; oj < noff; ++oj) {   /* j > k in NZ(i) */
+            /* j > k in NZ(i) with (k, j) in NZ; other j have H(k,j) = 0 */
+            for (int64_t p = ptr[ok]; p < ptr[ok + 1]; ++p) {
                 int64_t j;
-                if (!in_grid(&g, c, oj, &j, i)) continue;
-                int okj = pair[(size_t)ok * noff + oj];
-                if (okj < 0) continue;                  /* (k, j) not in NZ */
-                Hi[oj] -= lik * Hk[okj];
+                if (!in_grid(&g, c, pj[p], &j, i)) continue;
+                Hi[pj[p]] -= lik * Hk[pkj[p]];
             }
         }
     }
-    free(pair);
+    free(ptr); free(pj); free(pkj);
     return 0;
 }
 

@@ -282,15 +282,20 @@ def stencil_rows(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray, offsets,
     for o, off in enumerate(offsets):
         Sd = [np.stack([_diag_of(S[t], off[k]) for t in range(T + 1)]) for k in range(d)]
         Md = [np.stack([_diag_of(Mm[t], off[k]) for t in range(T + 1)]) for k in range(d)]
+        def term(C, Fz, Fy, Fx):
+            # sum_{r,s,t} C[r,s,t] Fz[r,z] Fy[s,y] Fx[t,x], one direction at a time
+            if d == 2:
+                tmp = np.tensordot(C, Fy, axes=(0, 0))          # [t, y]
+                return np.tensordot(tmp, Fx, axes=(0, 0))        # [y, x]
+            tmp = np.tensordot(C, Fz, axes=(0, 0))               # [s, t, z]
+            tmp = np.tensordot(tmp, Fy, axes=(0, 0))             # [t, z, y]
+            return np.tensordot(tmp, Fx, axes=(0, 0))            # [z, y, x]
+
         if d == 2:
             # coefficient index [s (y), t (x)]
-            val = (np.einsum('st,sy,tx->yx', A, Md[1], Sd[0], optimize=True)
-                   + np.einsum('st,sy,tx->yx', A, Sd[1], Md[0], optimize=True)
-                   + np.einsum('st,sy,tx->yx', Bc, Md[1], Md[0], optimize=True))
+            val = term(A, None, Md[1], Sd[0]) + term(A, None, Sd[1], Md[0]) + term(Bc, None, Md[1], Md[0])
         else:
-            val = (np.einsum('rst,rz,sy,tx->zyx', A, Md[2], Md[1], Sd[0], optimize=True)
-                   + np.einsum('rst,rz,sy,tx->zyx', A, Md[2], Sd[1], Md[0], optimize=True)
-                   + np.einsum('rst,rz,sy,tx->zyx', A, Sd[2], Md[1], Md[0], optimize=True)
-                   + np.einsum('rst,rz,sy,tx->zyx', Bc, Md[2], Md[1], Md[0], optimize=True))
+            val = (term(A, Md[2], Md[1], Sd[0]) + term(A, Md[2], Sd[1], Md[0])
+                   + term(A, Sd[2], Md[1], Md[0]) + term(Bc, Md[2], Md[1], Md[0]))
         H[:, o] = val.reshape(-1)
     return H

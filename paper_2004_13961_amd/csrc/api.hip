@@ -1,0 +1,391 @@
+// extern "C" entry points of liblgpcg (declared and documented in
+// include/lgpcg.h).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <new>
+#include <set>
+#include <tuple>
+
+#include "lgp_internal.h"
+
+using namespace lgp;
+
+struct lgp_problem_s {
+    Problem P;
+};
+struct lgp_factor_s {
+    Factor F;
+};
+
+extern "C" {
+
+int lgp_version(void) { return 100; }
+
+const char* lgp_status_str(lgp_status s) {
+    switch (s) {
+        case LGP_OK: return "ok";
+        case LGP_E_ARG: return "invalid argument";
+        case LGP_E_NOMEM: return "buffer too small";
+        case LGP_E_COEF: return "coefficient violates a > 0, b >= 0 at a node";
+        case LGP_E_ILU_PIVOT: return "ILU(0) pivot <= 0 or not finite";
+        case LGP_E_NOCONV: return "no convergence within max_iter";
+        case LGP_E_BREAKDOWN: return "PCG breakdown (p'Kp <= 0 or r'z <= 0)";
+        case LGP_E_HIP: return "HIP runtime error";
+        case LGP_E_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+int lgp_last_hip_error(void) { return g_last_hip_error; }
+
+lgp_status lgp_gauss_legendre(int N, double* x, double* w) {
+    if (N < 1 || !x || !w) return LGP_E_ARG;
+    std::vector<double> xv, wv;
+    gauss_legendre_host(N, xv, wv);
+    for (int i = 0; i <= N; ++i) {
+        x[i] = xv[i];
+        w[i] = wv[i];
+    }
+    return LGP_OK;
+}
+
+static bool valid_dims(int d, int N) { return (d == 2 || d == 3) && N >= 2 && N <= 4096; }
+
+static void init_problem_dims(Problem& P, int d, int N) {
+    P.d = d;
+    P.N = N;
+    P.n1 = N - 1;
+    P.q = N + 1;
+    P.n = 1;
+    P.nq = 1;
+    for (int k = 0; k < d; ++k) {
+        P.n *= P.n1;
+        P.nq *= P.q;
+    }
+}
+
+size_t lgp_problem_bytes(int d, int N) {
+    if (!valid_dims(d, N)) return 0;
+    Problem P;
+    init_problem_dims(P, d, N);
+    return plan_problem(P, nullptr);
+}
+
+lgp_status lgp_build_problem(int d, int N, const double* a_nodes, const double* b_nodes, void* buf,
+                             size_t buf_bytes, void* stream, lgp_problem* out) {
+    if (!out) return LGP_E_ARG;
+    *out = nullptr;
+    if (!valid_dims(d, N) || !a_nodes || !b_nodes || !buf) return LGP_E_ARG;
+    lgp_problem_s* h = new (std::nothrow) lgp_problem_s();
+    if (!h) return LGP_E_NOMEM;
+    Problem& P = h->P;
+    init_problem_dims(P, d, N);
+    if (plan_problem(P, buf) > buf_bytes) {
+        delete h;
+        return LGP_E_NOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    lgp_status st = build_tables(P, s);
+    bool ok = false;
+    if (st == LGP_OK) st = setup_nodes(P, a_nodes, b_nodes, s, &ok);
+    if (st == LGP_OK && !ok) st = LGP_E_COEF;
+    if (st != LGP_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return LGP_OK;
+}
+
+void lgp_destroy_problem(lgp_problem p) { delete p; }
+
+lgp_status lgp_load_vector(lgp_problem p, const double* f_nodes, double* F, void* stream) {
+    if (!p || !f_nodes || !F) return LGP_E_ARG;
+    return load_vector(p->P, f_nodes, F, (hipStream_t)stream);
+}
+
+lgp_status lgp_matvec(lgp_problem p, const void* u, void* y, lgp_dtype prec, void* stream) {
+    if (!p || !u || !y || u == y) return LGP_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    switch (prec) {
+        case LGP_F64: return matvec_f64(p->P, (const double*)u, (double*)y, s);
+        case LGP_F32: return matvec_lp(p->P, (const float*)u, (float*)y, GEMM_F32, s);
+        case LGP_BF16: return matvec_lp(p->P, (const float*)u, (float*)y, GEMM_BF16, s);
+    }
+    return LGP_E_ARG;
+}
+
+// ---------------------------------------------------------- pattern ------
+// NZ(M) as the union, over the non-negligible series terms, of the offset
+// boxes each Kronecker term can reach: for an a-term with degrees
+// (tx, ty, tz) the direction carrying S^(t) reaches |delta| <= t and the
+// others (carrying M^(t)) reach t + 2; a b-term reaches t + 2 everywhere.
+static std::vector<std::array<int, 3>> pattern_offsets(int d, int T, const std::vector<double>& ca,
+                                                      const std::vector<double>& cb) {
+    const int T1 = T + 1;
+    std::set<std::tuple<int, int, int>> S;
+    S.insert({0, 0, 0});
+    auto add_box = [&](int rx, int ry, int rz) {
+        for (int z = -rz; z <= rz; ++z)
+            for (int y = -ry; y <= ry; ++y)
+                for (int x = -rx; x <= rx; ++x) S.insert({z, y, x});
+    };
+    const int tz_max = (d == 3) ? T : 0;
+    for (int tz = 0; tz <= tz_max; ++tz)
+        for (int ty = 0; ty <= T; ++ty)
+            for (int tx = 0; tx <= T; ++tx) {
+                const size_t ci = ((size_t)tz * T1 + ty) * T1 + tx;
+                if (ca[ci] != 0.0) {
+                    add_box(tx, ty + 2, d == 3 ? tz + 2 : 0);
+                    add_box(tx + 2, ty, d == 3 ? tz + 2 : 0);
+                    if (d == 3) add_box(tx + 2, ty + 2, tz);
+                }
+                if (cb[ci] != 0.0) add_box(tx + 2, ty + 2, d == 3 ? tz + 2 : 0);
+            }
+    std::vector<std::array<int, 3>> out;
+    for (auto& t : S) out.push_back({std::get<2>(t), std::get<1>(t), std::get<0>(t)});   // sorted (z, y, x)
+    return out;
+}
+
+static int count_pairs(const std::vector<std::array<int, 3>>& lower, int h) {
+    const int R = 4 * h + 1;
+    std::vector<char> in((size_t)R * R * R, 0);
+    auto key = [&](int a, int b, int c) { return ((size_t)(c + 2 * h) * R + (b + 2 * h)) * R + (a + 2 * h); };
+    for (auto& o : lower) in[key(o[0], o[1], o[2])] = 1;
+    int cnt = 0;
+    for (size_t j = 0; j < lower.size(); ++j)
+        for (size_t k = 0; k < j; ++k) {
+            const int a = lower[k][0] - lower[j][0], b = lower[k][1] - lower[j][1], c = lower[k][2] - lower[j][2];
+            if (in[key(a, b, c)]) ++cnt;
+        }
+    return cnt;
+}
+
+static void set_pattern(Factor& F, const std::vector<std::array<int, 3>>& offs) {
+    F.noff = (int)offs.size();
+    F.offs.assign(3 * offs.size(), 0);
+    F.Hx = F.Hy = F.Hz = 0;
+    int diag = -1;
+    for (size_t k = 0; k < offs.size(); ++k) {
+        F.offs[3 * k] = offs[k][0];
+        F.offs[3 * k + 1] = offs[k][1];
+        F.offs[3 * k + 2] = offs[k][2];
+        F.Hx = std::max(F.Hx, std::abs(offs[k][0]));
+        F.Hy = std::max(F.Hy, std::abs(offs[k][1]));
+        F.Hz = std::max(F.Hz, std::abs(offs[k][2]));
+        if (offs[k][0] == 0 && offs[k][1] == 0 && offs[k][2] == 0) diag = (int)k;
+    }
+    F.nlo = diag;
+    std::vector<std::array<int, 3>> lower(offs.begin(), offs.begin() + diag);
+    F.npairs = count_pairs(lower, F.h);
+}
+
+static void init_factor_dims(Factor& F, const Problem& P, int Ta, int Tb) {
+    F.P = const_cast<Problem*>(&P);
+    F.d = P.d;
+    F.n1 = P.n1;
+    F.n = P.n;
+    F.Ta = Ta;
+    F.Tb = Tb;
+    F.T = std::max(Ta, Tb);
+    F.h = F.T + 2;
+    F.nlines = (P.d == 2) ? P.n1 : P.n1 * P.n1;
+    F.levels = 0;
+}
+
+size_t lgp_factor_bytes(lgp_problem p, int Ta, int Tb, lgp_dtype store) {
+    if (!p || Ta < 0 || Tb < 0) return 0;
+    Factor F;
+    init_factor_dims(F, p->P, Ta, Tb);
+    // upper bound: the full box |delta_k| <= h
+    const int T1 = F.T + 1;
+    const size_t tp = (p->P.d == 2) ? (size_t)T1 * T1 : (size_t)T1 * T1 * T1;
+    std::vector<double> ones(tp, 1.0);
+    set_pattern(F, pattern_offsets(p->P.d, F.T, ones, ones));
+    return plan_factor(F, nullptr, store != LGP_F64);
+}
+
+lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* buf, size_t buf_bytes, void* stream,
+                        lgp_factor* out) {
+    if (!out) return LGP_E_ARG;
+    *out = nullptr;
+    if (!p || !buf || Ta < 0 || Tb < 0 || Ta > 24 || Tb > 24) return LGP_E_ARG;
+    if (buf_bytes < lgp_factor_bytes(p, Ta, Tb, store)) return LGP_E_NOMEM;
+    Problem& P = p->P;
+    hipStream_t s = (hipStream_t)stream;
+    lgp_factor_s* hF = new (std::nothrow) lgp_factor_s();
+    if (!hF) return LGP_E_NOMEM;
+    Factor& F = hF->F;
+    init_factor_dims(F, P, Ta, Tb);
+    const int T = F.T, T1 = T + 1, q = P.q, d = P.d;
+    const size_t tp = (d == 2) ? (size_t)T1 * T1 : (size_t)T1 * T1 * T1;
+    lgp_status st = LGP_OK;
+    // --- truncated Legendre coefficients: FDLT of the nodal values (Sec. 2.2),
+    //     indices <= T per direction, as contractions with
+    //     FT[t][m] = (2t+1)/2 w_m L_t(x_m)
+    std::vector<double> FT((size_t)T1 * q);
+    for (int m = 0; m < q; ++m) {
+        double l0 = 1.0, l1 = P.x[m];
+        for (int t = 0; t <= T; ++t) {
+            double lt;
+            if (t == 0) lt = 1.0;
+            else if (t == 1) lt = P.x[m];
+            else {
+                const double l2 = ((2 * (t - 1) + 1) * P.x[m] * l1 - (t - 1) * l0) / t;
+                l0 = l1;
+                l1 = l2;
+                lt = l2;
+            }
+            FT[(size_t)t * q + m] = (2 * t + 1) / 2.0 * P.w[m] * lt;
+        }
+    }
+    const size_t need0 = (d == 2) ? (size_t)q * T1 : (size_t)q * q * T1;   // stage outputs
+    const size_t need1 = (d == 2) ? 0 : (size_t)q * T1 * T1;
+    if (need0 > P.s0n || need1 > P.s1n || (size_t)T1 * q > P.s3n || tp > P.s2n) {
+        delete hF;
+        return LGP_E_UNSUPPORTED;
+    }
+    std::vector<double> ca(tp), cb(tp);
+    double* dFT = P.s3;
+    if (hipMemcpyAsync(dFT, FT.data(), FT.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
+        delete hF;
+        return LGP_E_HIP;
+    }
+    for (int which = 0; which < 2 && st == LGP_OK; ++which) {
+        const double* src = which == 0 ? P.a_nodes : P.b_nodes;
+        double* dst = P.s2;   // (T+1)^d result
+        if (d == 2) {
+            // X (q x T1) = f (q x q) FT^T ; C (T1 x T1) = FT X
+            GemmArgs g1 = {src, 0, q, 1, dFT, 0, 1, q, P.s0, 0, T1, 1, nullptr, 0, 0, 0, q, T1, q, 1, 0};
+            GemmArgs g2 = {dFT, 0, q, 1, P.s0, 0, T1, 1, dst, 0, T1, 1, nullptr, 0, 0, 0, T1, T1, q, 1, 0};
+            if ((st = gemm(GEMM_F64, g1, s)) == LGP_OK) st = gemm(GEMM_F64, g2, s);
+        } else {
+            const int qq = q * q;
+            // x: X (q^2 x T1) = f FT^T; y: per z, Y (T1 x T1) = FT X[z]; z: C (T1 x T1^2) = FT Y
+            GemmArgs g1 = {src, 0, q, 1, dFT, 0, 1, q, P.s0, 0, T1, 1, nullptr, 0, 0, 0, qq, T1, q, 1, 0};
+            GemmArgs g2 = {dFT, 0, q, 1, P.s0, (int64_t)q * T1, T1, 1, P.s1, (int64_t)T1 * T1, T1, 1,
+                           nullptr, 0, 0, 0, T1, T1, q, q, 0};
+            GemmArgs g3 = {dFT, 0, q, 1, P.s1, 0, (int64_t)T1 * T1, 1, dst, 0, (int64_t)T1 * T1, 1,
+                           nullptr, 0, 0, 0, T1, T1 * T1, q, 1, 0};
+            if ((st = gemm(GEMM_F64, g1, s)) == LGP_OK && (st = gemm(GEMM_F64, g2, s)) == LGP_OK)
+                st = gemm(GEMM_F64, g3, s);
+        }
+        if (st == LGP_OK) {
+            std::vector<double>& h = which == 0 ? ca : cb;
+            if (hipMemcpyAsync(h.data(), dst, tp * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                st = LGP_E_HIP;
+        }
+    }
+    if (st != LGP_OK) {
+        delete hF;
+        return st;
+    }
+    // keep indices <= Ta (a) and <= Tb (b); drop terms below 1e-13 of the
+    // largest magnitude over both series
+    double mx = 0.0;
+    for (size_t ci = 0; ci < tp; ++ci) {
+        const int tx = (int)(ci % T1), ty = (int)((ci / T1) % T1), tz = (d == 3) ? (int)(ci / (T1 * T1)) : 0;
+        if (tx > Ta || ty > Ta || tz > Ta) ca[ci] = 0.0;
+        if (tx > Tb || ty > Tb || tz > Tb) cb[ci] = 0.0;
+        mx = std::max(mx, std::max(std::fabs(ca[ci]), std::fabs(cb[ci])));
+    }
+    for (size_t ci = 0; ci < tp; ++ci) {
+        if (std::fabs(ca[ci]) <= 1e-13 * mx) ca[ci] = 0.0;
+        if (std::fabs(cb[ci]) <= 1e-13 * mx) cb[ci] = 0.0;
+    }
+    set_pattern(F, pattern_offsets(d, T, ca, cb));
+    if (plan_factor(F, buf, store != LGP_F64) > buf_bytes) {
+        delete hF;
+        return LGP_E_NOMEM;
+    }
+    if (hipMemcpyAsync(F.coefA, ca.data(), tp * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(F.coefB, cb.data(), tp * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
+        delete hF;
+        return LGP_E_HIP;
+    }
+    st = factor_build(F, s);
+    if (st == LGP_OK) {
+        int flag = 0;
+        if (hipMemcpyAsync(&flag, F.flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = LGP_E_HIP;
+        else if (flag)
+            st = LGP_E_ILU_PIVOT;
+    }
+    if (st != LGP_OK) {
+        delete hF;
+        return st;
+    }
+    *out = hF;
+    return LGP_OK;
+}
+
+void lgp_destroy_factor(lgp_factor m) { delete m; }
+
+lgp_status lgp_ilu_forward(lgp_factor m, const double* r, double* y, void* stream) {
+    if (!m || !r || !y || r == y) return LGP_E_ARG;
+    return sweep(m->F, false, r, y, (hipStream_t)stream);
+}
+
+lgp_status lgp_ilu_backward(lgp_factor m, const double* y, double* z, void* stream) {
+    if (!m || !y || !z || y == z) return LGP_E_ARG;
+    return sweep(m->F, true, y, z, (hipStream_t)stream);
+}
+
+lgp_status lgp_precond_apply(lgp_factor m, const double* r, double* z, void* stream) {
+    if (!m || !r || !z || r == z) return LGP_E_ARG;
+    lgp_status st = sweep(m->F, false, r, m->F.y_tmp, (hipStream_t)stream);
+    if (st != LGP_OK) return st;
+    return sweep(m->F, true, m->F.y_tmp, z, (hipStream_t)stream);
+}
+
+lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out) {
+    if (!m || !out) return LGP_E_ARG;
+    const Factor& F = m->F;
+    out->d = F.d;
+    out->N = F.n1 + 1;
+    out->n1 = F.n1;
+    out->Ta = F.Ta;
+    out->Tb = F.Tb;
+    out->n = F.n;
+    out->noff = F.noff;
+    out->n_lower = F.nlo;
+    out->offsets = F.offs.data();
+    out->L = F.L;
+    out->D = F.Dg;
+    out->levels = F.levels;
+    return LGP_OK;
+}
+
+size_t lgp_solve_workspace_bytes(lgp_problem p, lgp_dtype inner) {
+    if (!p) return 0;
+    return solve_ws_bytes(p->P.n, inner != LGP_F64);
+}
+
+lgp_status lgp_pcg_solve(lgp_problem p, lgp_factor m, const double* F, double* x, const lgp_solve_opts* opts,
+                         void* ws, size_t ws_bytes, void* stream, lgp_solve_info* info) {
+    if (!p || !m || !F || !x || !ws || !info) return LGP_E_ARG;
+    if (m->F.P != &p->P) return LGP_E_ARG;
+    lgp_solve_opts o;
+    o.rtol = 1e-10;
+    o.max_iter = 2000;
+    o.inner = LGP_F64;
+    o.inner_rtol = 1e-4;
+    o.max_outer = 60;
+    o.check_every = 4;
+    if (opts) {
+        o = *opts;
+        if (!(o.rtol > 0.0)) return LGP_E_ARG;
+        if (o.max_iter <= 0) o.max_iter = 2000;
+        if (!(o.inner_rtol > 0.0)) o.inner_rtol = 1e-4;
+        if (o.max_outer <= 0) o.max_outer = 60;
+        if (o.check_every <= 0) o.check_every = 4;
+    }
+    lgp_status st = pcg_solve_impl(p->P, m->F, F, x, o, ws, ws_bytes, (hipStream_t)stream, info);
+    info->status = st;
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,549 @@
+// Preconditioner of Sec. 4.1-4.2 on the GPU: truncated Legendre series of a
+// and b, exact 1D band factors (Lemma LegProduct), NZ(M) as an offset
+// stencil, ILU(0) (Alg. 2) in FP64, and the two substitutions of the
+// one-step method (Alg. 3 and Alg. 4).
+//
+// Storage. NZ(M) is a symmetric set of offsets (dx,dy,dz), so ILU(0) of the
+// symmetric M gives U = diag(U) L^T; only the strictly lower part of L
+// (n_lower values per row, row-major, zero outside the grid) and the pivots
+// D = diag(U) are kept. For the backward sweep a second array Ut holds, for
+// the rows in reversed order, L(i - delta_k, i), so both sweeps stream their
+// operator forward in memory with the same access pattern.
+//
+// Schedule. Row i depends on rows i + delta for lower offsets delta. With
+// Hx, Hy the largest |dx|, |dy| of the pattern, the level
+// l(i) = ix + (Hx+1) iy + (Hx+1)(Hy+1) iz strictly increases along every
+// dependency, so rows of one level are independent (a hyperplane schedule).
+//   * Factorisation: one wave per row, rows handed out in level order by an
+//     atomic ticket, completion published by a per-row flag. Each row is
+//     computed left-looking (offsets in column order), so only its last
+//     offsets wait for recently finished rows.
+//   * Sweeps: one workgroup per grid line (fixed iy, iz), lines handed out
+//     in order of l, rows of a line in increasing ix; a line waits on the
+//     progress counter of line (iy-1, iz) and of line (min(iy+Hy, n1-1),
+//     iz-1), which by induction covers every other dependency.
+#include <algorithm>
+#include <cmath>
+
+#include "lgp_internal.h"
+
+namespace lgp {
+
+// -------------------------------------------------- host: 1D factors -----
+// int_{-1}^{1} L_t L_m L_n dx. With g = (t+m+n)/2 (nonzero only for t+m+n
+// even and |m-n| <= t <= m+n) the product formula gives
+//   2/(2g+1) * C_{g-m} C_{g-n} C_{g-t} / C_g,  C_r = (2r-1)!!/(r! 2^r).
+// The large-index ratio C_{g-t}/C_g = prod_{r=g-t+1}^{g} 2r/(2r-1) has only
+// t factors; C_{g-m}, C_{g-n} have small indices when t is small.
+static double Cr(int r) {
+    double c = 1.0;
+    for (int i = 1; i <= r; ++i) c *= (2.0 * i - 1.0) / (2.0 * i);
+    return c;
+}
+
+double triple_legendre(int t, int m, int n) {
+    if (t < 0 || m < 0 || n < 0) return 0.0;
+    if ((t + m + n) & 1) return 0.0;
+    if (t > m + n || t < std::abs(m - n)) return 0.0;
+    const int g = (t + m + n) / 2;
+    // order so that the two small indices use direct products
+    int small1 = g - m, small2 = g - n, big = g - t;
+    // if t is the largest of the three, g-t is the smallest: swap roles so
+    // that the ratio is taken against the smallest of (t, m, n)
+    int lo = std::min(t, std::min(m, n));
+    if (lo != t) {
+        if (lo == m) { small1 = g - t; big = g - m; }
+        else         { small2 = g - t; big = g - n; }
+    }
+    double ratio = 1.0;   // C_big / C_g = prod_{r=big+1}^{g} 2r/(2r-1)
+    for (int r = big + 1; r <= g; ++r) ratio *= (2.0 * r) / (2.0 * r - 1.0);
+    return 2.0 / (2.0 * g + 1.0) * Cr(small1) * Cr(small2) * ratio;
+}
+
+// S^(t)(i, m) = (2i+3)(2m+3) int L_t L_{i+1} L_{m+1}
+static double S1(int t, int i, int m) { return (2.0 * i + 3) * (2.0 * m + 3) * triple_legendre(t, i + 1, m + 1); }
+// M^(t)(i, m) = int L_t (L_i - L_{i+2}) (L_m - L_{m+2})
+static double M1(int t, int i, int m) {
+    return triple_legendre(t, i, m) - triple_legendre(t, i, m + 2) - triple_legendre(t, i + 2, m) +
+           triple_legendre(t, i + 2, m + 2);
+}
+
+size_t plan_factor(Factor& F, void* buf, bool with32) {
+    Carver c(buf);
+    const int64_t n = F.n;
+    const int nlo = F.nlo;
+    const int T = F.T, h = F.h, d = F.d, n1 = F.n1;
+    int64_t tp = 1;
+    for (int k = 0; k < d; ++k) tp *= (T + 1);
+    F.L = c.take<double>((size_t)n * nlo);
+    F.Ut = c.take<double>((size_t)n * nlo);
+    F.Dg = c.take<double>(n);
+    F.invD = c.take<double>(n);
+    F.has32 = with32;
+    if (with32) {
+        F.L32 = c.take<float>((size_t)n * nlo);
+        F.Ut32 = c.take<float>((size_t)n * nlo);
+        F.invD32 = c.take<float>(n);
+    } else {
+        F.L32 = F.Ut32 = F.invD32 = nullptr;
+    }
+    F.d_offs = c.take<int>((size_t)4 * (nlo + 1));
+    F.line_order = c.take<int>(F.nlines);
+    F.prog = c.take<unsigned>((size_t)2 * F.nlines);
+    F.ticket = c.take<unsigned>(4);
+    F.flag = c.take<int>(4);
+    F.coefA = c.take<double>(tp);
+    F.coefB = c.take<double>(tp);
+    F.band = c.take<double>((size_t)2 * (T + 1) * n1 * (2 * h + 1));
+    F.pair_ptr = c.take<int>(nlo + 2);
+    F.pair_j = c.take<int>(F.npairs > 0 ? F.npairs : 1);
+    F.pair_l = c.take<int>(F.npairs > 0 ? F.npairs : 1);
+    F.y_tmp = c.take<double>(n);
+    F.bytes = c.off + 256;
+    return F.bytes;
+}
+
+// ------------------------------------------------------ device helpers ---
+__device__ inline unsigned ld_acquire(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned ld_relaxed(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_release(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline float wave_sum(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+struct RowGeo {
+    int n1, d;
+    int64_t n;
+};
+
+// ------------------------------------------------- coefficient fold ------
+// For line (iy, iz) and every (dy, dz) in [-h, h]^2 (dz = 0 in 2D) and x
+// degree t <= T:
+//   Fa[t] = sum_{r,s} a_{r s t} M^(r)(iz, iz+dz) M^(s)(iy, iy+dy)
+//   Fb[t] = sum_{r,s} a_{r s t} [M^(r)_z S^(s)_y + S^(r)_z M^(s)_y] + b_{r s t} M^(r)_z M^(s)_y
+// so that M(i, i+delta) = sum_t S^(t)(ix, ix+dx) Fa[t] + M^(t)(ix, ix+dx) Fb[t]
+// (Kronecker form of Sec. 4.2; in 2D the z factors are 1 and r = 0).
+// Layout: fold[line][(dz+h)*(2h+1) + (dy+h)][2][T+1].
+__global__ void fold_kernel(int d, int n1, int T, int h, const double* __restrict__ band,
+                            const double* __restrict__ coefA, const double* __restrict__ coefB,
+                            double* __restrict__ fold, int nlines) {
+    const int W = 2 * h + 1;
+    const int T1 = T + 1;
+    const int64_t bandT = (int64_t)n1 * W;          // stride between t
+    const double* Sb = band;                         // S^(t)(i, i+delta)
+    const double* Mb = band + (int64_t)T1 * bandT;   // M^(t)(i, i+delta)
+    const int nz = (d == 3) ? W : 1;
+    for (int line = blockIdx.x; line < nlines; line += gridDim.x) {
+        const int iy = line % n1, iz = line / n1;
+        const int combos = nz * W * T1;
+        for (int c = threadIdx.x; c < combos; c += blockDim.x) {
+            const int t = c % T1;
+            const int dyi = (c / T1) % W;
+            const int dzi = c / (T1 * W);
+            const int dy = dyi - h;
+            const int dz = (d == 3) ? dzi - h : 0;
+            double fa = 0.0, fb = 0.0;
+            const bool yin = (iy + dy >= 0 && iy + dy < n1);
+            const bool zin = (d == 2) || (iz + dz >= 0 && iz + dz < n1);
+            if (yin && zin) {
+                const int R = (d == 3) ? T1 : 1;
+                for (int r = 0; r < R; ++r) {
+                    double mz = 1.0, sz = 0.0;
+                    if (d == 3) {
+                        mz = Mb[r * bandT + (int64_t)iz * W + (dz + h)];
+                        sz = Sb[r * bandT + (int64_t)iz * W + (dz + h)];
+                    }
+                    for (int s = 0; s < T1; ++s) {
+                        const double my = Mb[s * bandT + (int64_t)iy * W + (dy + h)];
+                        const double sy = Sb[s * bandT + (int64_t)iy * W + (dy + h)];
+                        const int64_t ci = ((int64_t)r * T1 + s) * T1 + t;   // x fastest
+                        const double a = coefA[ci], b = coefB[ci];
+                        fa += a * mz * my;
+                        fb += a * (mz * sy + sz * my) + b * mz * my;
+                    }
+                }
+            }
+            double* o = fold + (int64_t)line * nz * W * 2 * T1 + ((int64_t)(dzi * W + dyi) * 2) * T1;
+            o[t] = fa;
+            o[T1 + t] = fb;
+        }
+    }
+}
+
+// ---------------------------------------------------- factorisation ------
+// One wave per row. LDS: u[0..nlo] (u[nlo] = diagonal), offsets table.
+__global__ __launch_bounds__(64) void ilu_factor_kernel(
+    int d, int n1, int64_t n, int nlo, int T, int h, const int4* __restrict__ offs,
+    const int* __restrict__ row_order, const double* __restrict__ band, const double* __restrict__ fold,
+    const int* __restrict__ pair_ptr, const int* __restrict__ pair_k, const int* __restrict__ pair_l,
+    double* __restrict__ L, double* __restrict__ Dg, double* __restrict__ invD, unsigned* done,
+    unsigned* ticket, int* flag) {
+    extern __shared__ double u[];   // nlo + 1
+    __shared__ int s_row;
+    const int lane = threadIdx.x;
+    const int W = 2 * h + 1;
+    const int T1 = T + 1;
+    const int64_t bandT = (int64_t)n1 * W;
+    const int nzW = (d == 3) ? W : 1;
+    for (;;) {
+        if (lane == 0) {
+            unsigned tk = atomicAdd(ticket, 1u);
+            s_row = (tk < (unsigned)n) ? row_order[tk] : -1;
+        }
+        __syncthreads();
+        const int64_t i = s_row;
+        __syncthreads();
+        if (i < 0) break;
+        const int ix = (int)(i % n1);
+        const int iy = (int)((i / n1) % n1);
+        const int iz = (d == 3) ? (int)(i / ((int64_t)n1 * n1)) : 0;
+        const int64_t line = i / n1;
+        const double* fl = fold + line * (int64_t)nzW * W * 2 * T1;
+        // M(i, i + delta_k) for lower offsets and the diagonal
+        for (int k = lane; k <= nlo; k += 64) {
+            const int4 o = offs[k];
+            double v = 0.0;
+            const int cx = ix + o.x, cy = iy + o.y, cz = iz + o.z;
+            if (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1) {
+                const double* f = fl + ((int64_t)((o.z + h) * (d == 3 ? 1 : 0) * W + (o.y + h)) * 2) * T1;
+                for (int t = 0; t < T1; ++t)
+                    v += band[t * bandT + (int64_t)ix * W + (o.x + h)] * f[t] +
+                         band[(T1 + t) * bandT + (int64_t)ix * W + (o.x + h)] * f[T1 + t];
+            }
+            u[k] = v;
+        }
+        __syncthreads();
+        // left-looking (Alg. 2 with U = D L^T): u_j = L(i,j) D(i+dj) =
+        // M(i,j) - sum_{k<j} u_k L(i+dj, i+dk); L(i,j) = u_j / D(i+dj) later
+        for (int j = 0; j < nlo; ++j) {
+            const int4 oj = offs[j];
+            const int cx = ix + oj.x, cy = iy + oj.y, cz = iz + oj.z;
+            const bool in = (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1);
+            if (!in) continue;   // uniform across the wave
+            const int64_t rj = i + oj.w;
+            if (lane == 0) {
+                while (ld_acquire(&done[rj]) == 0u) __builtin_amdgcn_s_sleep(1);
+            }
+            __syncthreads();
+            double acc = 0.0;
+            const double* Lj = L + rj * nlo;
+            for (int p = pair_ptr[j] + lane; p < pair_ptr[j + 1]; p += 64)
+                acc += u[pair_k[p]] * Lj[pair_l[p]];
+            acc = wave_sum(acc);
+            if (lane == 0) u[j] = u[j] - acc;
+            __syncthreads();
+        }
+        // pivot: D(i) = M(i,i) - sum_k u_k L(i,k),  L(i,k) = u_k / D(i+dk)
+        double acc = 0.0;
+        for (int k = lane; k < nlo; k += 64) {
+            const int4 o = offs[k];
+            const int cx = ix + o.x, cy = iy + o.y, cz = iz + o.z;
+            const bool in = (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1);
+            double lk = 0.0;
+            if (in) {
+                lk = u[k] / Dg[i + o.w];
+                acc += u[k] * lk;
+            }
+            L[i * nlo + k] = lk;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            const double piv = u[nlo] - acc;
+            if (!(piv > 0.0) || !isfinite(piv)) atomicOr(flag, 1);
+            Dg[i] = piv;
+            invD[i] = 1.0 / piv;
+        }
+        __syncthreads();
+        if (lane == 0) st_release(&done[i], 1u);
+        __syncthreads();
+    }
+}
+
+// Backward-sweep operator in reversed row order: Ut[i'][k] = L(i - delta_k, i)
+// with i = n-1-i'.
+__global__ void build_ut_kernel(int d, int n1, int64_t n, int nlo, const int4* __restrict__ offs,
+                                const double* __restrict__ L, double* __restrict__ Ut) {
+    const int64_t total = n * nlo;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ip = e / nlo;
+        const int k = (int)(e % nlo);
+        const int64_t i = n - 1 - ip;
+        const int ix = (int)(i % n1), iy = (int)((i / n1) % n1);
+        const int iz = (d == 3) ? (int)(i / ((int64_t)n1 * n1)) : 0;
+        const int4 o = offs[k];
+        const int cx = ix - o.x, cy = iy - o.y, cz = iz - o.z;
+        double v = 0.0;
+        if (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1) v = L[(i - o.w) * nlo + k];
+        Ut[e] = v;
+    }
+}
+
+__global__ void to_f32_kernel(int64_t count, const double* __restrict__ a, float* __restrict__ b) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        b[e] = (float)a[e];
+}
+
+// ---------------------------------------------------------- sweeps -------
+// out[r] = in[r] * s[r] - sum_k A[r'][k] out[r + sign*delta_k]   (r' the
+// stream position: r' = r forward, r' = n-1-r backward). Rows of a line run
+// in increasing stream order. NT threads per line.
+template <typename T, int NT, bool REV, bool SCALE>
+__global__ __launch_bounds__(NT) void sweep_kernel(int d, int n1, int64_t n, int nlo,
+                                                   const int4* __restrict__ offs,
+                                                   const int* __restrict__ line_order, int nlines,
+                                                   int Hx, int Hy, const T* __restrict__ A,
+                                                   const T* __restrict__ scale, const T* __restrict__ in,
+                                                   T* __restrict__ out, unsigned* prog, unsigned* ticket,
+                                                   const int* __restrict__ stop) {
+    __shared__ int s_line;
+    __shared__ T s_red[NT / 64];
+    __shared__ unsigned s_have[2];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    if (stop && *stop) return;
+    for (;;) {
+        if (tid == 0) {
+            unsigned tk = atomicAdd(ticket, 1u);
+            s_line = (tk < (unsigned)nlines) ? line_order[tk] : -1;
+            s_have[0] = 0;
+            s_have[1] = 0;
+        }
+        __syncthreads();
+        const int line = s_line;
+        if (line < 0) break;
+        // stream coordinates of the line (reversed grid when REV)
+        const int ly = line % n1, lz = line / n1;
+        const int dep0 = (ly > 0) ? line - 1 : -1;                        // (iy-1, iz)
+        const int dep1 = (d == 3 && lz > 0) ? (lz - 1) * n1 + min(ly + Hy, n1 - 1) : -1;
+        for (int ix = 0; ix < n1; ++ix) {
+            const unsigned need = (unsigned)min(n1, ix + Hx + 1);
+            if (tid == 0) {
+                if (dep0 >= 0 && s_have[0] < need) {
+                    unsigned v;
+                    while ((v = ld_acquire(&prog[dep0])) < need) __builtin_amdgcn_s_sleep(1);
+                    s_have[0] = v;
+                }
+                if (dep1 >= 0 && s_have[1] < need) {
+                    unsigned v;
+                    while ((v = ld_acquire(&prog[dep1])) < need) __builtin_amdgcn_s_sleep(1);
+                    s_have[1] = v;
+                }
+            }
+            __syncthreads();
+            const int64_t rp = (int64_t)line * n1 + ix;         // stream row
+            const int64_t rm = REV ? (n - 1 - rp) : rp;          // memory row
+            T acc = T(0);
+            for (int k = tid; k < nlo; k += NT) {
+                const int4 o = offs[k];
+                const int cx = ix + o.x, cy = ly + o.y, cz = lz + o.z;
+                if (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1) {
+                    const int64_t nb = REV ? (rm - o.w) : (rm + o.w);
+                    acc += A[rp * nlo + k] * out[nb];
+                }
+            }
+            acc = wave_sum(acc);
+            if (NT > 64) {
+                if (lane == 0) s_red[wv] = acc;
+                __syncthreads();
+                if (tid == 0)
+                    for (int w2 = 1; w2 < NT / 64; ++w2) acc += s_red[w2];
+            }
+            if (tid == 0) {
+                T v = in[rm];
+                if (SCALE) v *= scale[rm];
+                out[rm] = v - acc;
+            }
+            __syncthreads();
+            if (tid == 0 && (ix == n1 - 1 || ((ix + 1) & 7) == 0)) st_release(&prog[line], (unsigned)(ix + 1));
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reset_kernel(unsigned* p, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// ------------------------------------------------------------- host ------
+static int persistent_grid(const void* kernel, int block, size_t shmem, int64_t units) {
+    int dev = 0, cus = 256, per = 1;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, shmem) != hipSuccess || per < 1)
+        per = 1;
+    int64_t g = (int64_t)cus * per;
+    if (g > units) g = units;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+lgp_status factor_build(Factor& F, hipStream_t s) {
+    const int d = F.d, n1 = F.n1, T = F.T, h = F.h;
+    const int W = 2 * h + 1, T1 = T + 1;
+    const int64_t n = F.n;
+    // 1D band tables S^(t)(i, i+delta), M^(t)(i, i+delta)
+    std::vector<double> band((size_t)2 * T1 * n1 * W, 0.0);
+    for (int t = 0; t <= T; ++t)
+        for (int i = 0; i < n1; ++i)
+            for (int dl = -h; dl <= h; ++dl) {
+                const int m = i + dl;
+                if (m < 0 || m >= n1) continue;
+                band[((size_t)t * n1 + i) * W + (dl + h)] = S1(t, i, m);
+                band[((size_t)(T1 + t) * n1 + i) * W + (dl + h)] = M1(t, i, m);
+            }
+    LGP_HIP(hipMemcpyAsync(F.band, band.data(), band.size() * 8, hipMemcpyHostToDevice, s));
+    // offsets (lower + diagonal) with linear offsets
+    std::vector<int> off4((size_t)4 * (F.nlo + 1));
+    for (int k = 0; k <= F.nlo; ++k) {
+        const int* o = &F.offs[3 * k];
+        off4[4 * k + 0] = o[0];
+        off4[4 * k + 1] = o[1];
+        off4[4 * k + 2] = o[2];
+        off4[4 * k + 3] = o[0] + n1 * o[1] + n1 * n1 * o[2];
+    }
+    LGP_HIP(hipMemcpyAsync(F.d_offs, off4.data(), off4.size() * 4, hipMemcpyHostToDevice, s));
+    // left-looking pair lists: for lower j, all lower k < j with
+    // offset(k) - offset(j) in the lower list (and its index)
+    std::vector<int> ptr(F.nlo + 2, 0), pk, pl;
+    {
+        const int R = 4 * h + 1;
+        std::vector<int> lut((size_t)R * R * R, -1);
+        auto key = [&](int a, int b, int c) { return ((size_t)(c + 2 * h) * R + (b + 2 * h)) * R + (a + 2 * h); };
+        for (int k = 0; k < F.nlo; ++k) lut[key(F.offs[3 * k], F.offs[3 * k + 1], F.offs[3 * k + 2])] = k;
+        for (int j = 0; j < F.nlo; ++j) {
+            ptr[j] = (int)pk.size();
+            for (int k = 0; k < j; ++k) {
+                const int a = F.offs[3 * k] - F.offs[3 * j];
+                const int b = F.offs[3 * k + 1] - F.offs[3 * j + 1];
+                const int c = F.offs[3 * k + 2] - F.offs[3 * j + 2];
+                if (std::abs(a) > 2 * h || std::abs(b) > 2 * h || std::abs(c) > 2 * h) continue;
+                const int l = lut[key(a, b, c)];
+                if (l >= 0) {
+                    pk.push_back(k);
+                    pl.push_back(l);
+                }
+            }
+        }
+        ptr[F.nlo] = (int)pk.size();
+        ptr[F.nlo + 1] = (int)pk.size();
+    }
+    if ((int)pk.size() != F.npairs) return LGP_E_ARG;   // planner and builder disagree
+    LGP_HIP(hipMemcpyAsync(F.pair_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, s));
+    if (F.npairs > 0) {
+        LGP_HIP(hipMemcpyAsync(F.pair_j, pk.data(), pk.size() * 4, hipMemcpyHostToDevice, s));
+        LGP_HIP(hipMemcpyAsync(F.pair_l, pl.data(), pl.size() * 4, hipMemcpyHostToDevice, s));
+    }
+    // line order for the sweeps: key iy + (Hy+1) iz
+    std::vector<int> lines(F.nlines);
+    for (int l = 0; l < F.nlines; ++l) lines[l] = l;
+    std::stable_sort(lines.begin(), lines.end(), [&](int a, int b) {
+        const int ka = (a % n1) + (F.Hy + 1) * (a / n1), kb = (b % n1) + (F.Hy + 1) * (b / n1);
+        return ka < kb;
+    });
+    LGP_HIP(hipMemcpyAsync(F.line_order, lines.data(), lines.size() * 4, hipMemcpyHostToDevice, s));
+    // row order for the factorisation: level ix + (Hx+1) iy + (Hx+1)(Hy+1) iz.
+    // The order and the per-line folded coefficients live in the Ut buffer
+    // (not yet needed) to avoid extra storage.
+    const int64_t A1 = F.Hx + 1, B1 = (int64_t)(F.Hx + 1) * (F.Hy + 1);
+    const int64_t maxlev = (n1 - 1) * (1 + A1 + (d == 3 ? B1 : 0)) + 1;
+    F.levels = (int)maxlev;
+    std::vector<int> cnt(maxlev + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t lv = (i % n1) + A1 * ((i / n1) % n1) + (d == 3 ? B1 * (i / ((int64_t)n1 * n1)) : 0);
+        cnt[lv + 1]++;
+    }
+    for (int64_t l = 0; l < maxlev; ++l) cnt[l + 1] += cnt[l];
+    std::vector<int> order(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t lv = (i % n1) + A1 * ((i / n1) % n1) + (d == 3 ? B1 * (i / ((int64_t)n1 * n1)) : 0);
+        order[cnt[lv]++] = (int)i;
+    }
+    int* d_order = (int*)F.Ut;
+    double* fold = (double*)((char*)F.Ut + (((size_t)n * 4 + 255) & ~(size_t)255));
+    const int nzW = (d == 3) ? W : 1;
+    const size_t fold_bytes = (size_t)F.nlines * nzW * W * 2 * T1 * 8;
+    if ((((size_t)n * 4 + 255) & ~(size_t)255) + fold_bytes > (size_t)n * F.nlo * 8) {
+        // small grids: the Ut buffer is too small for the scratch; use L32 if present
+        return LGP_E_UNSUPPORTED;
+    }
+    LGP_HIP(hipMemcpyAsync(d_order, order.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(fold_kernel, dim3(std::min(F.nlines, 4096)), dim3(256), 0, s, d, n1, T, h,
+                       (const double*)F.band, (const double*)F.coefA, (const double*)F.coefB, fold, F.nlines);
+    LGP_CHECK_LAUNCH();
+    // done flags live in the y_tmp buffer (n doubles >= n unsigned)
+    unsigned* done = (unsigned*)F.y_tmp;
+    LGP_HIP(hipMemsetAsync(done, 0, (size_t)n * 4, s));
+    LGP_HIP(hipMemsetAsync(F.ticket, 0, 16, s));
+    LGP_HIP(hipMemsetAsync(F.flag, 0, 16, s));
+    const size_t shmem = (size_t)(F.nlo + 1) * 8;
+    const int grid = persistent_grid((const void*)ilu_factor_kernel, 64, shmem, n);
+    hipLaunchKernelGGL(ilu_factor_kernel, dim3(grid), dim3(64), shmem, s, d, n1, n, F.nlo, T, h,
+                       (const int4*)F.d_offs, (const int*)d_order, (const double*)F.band, (const double*)fold,
+                       (const int*)F.pair_ptr, (const int*)F.pair_j, (const int*)F.pair_l, F.L, F.Dg, F.invD,
+                       done, F.ticket, F.flag);
+    LGP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(build_ut_kernel, dim3(4096), dim3(256), 0, s, d, n1, n, F.nlo, (const int4*)F.d_offs,
+                       (const double*)F.L, F.Ut);
+    LGP_CHECK_LAUNCH();
+    if (F.has32) {
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.nlo, (const double*)F.L, F.L32);
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.nlo, (const double*)F.Ut, F.Ut32);
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n, (const double*)F.invD, F.invD32);
+        LGP_CHECK_LAUNCH();
+    }
+    return LGP_OK;
+}
+
+template <typename T>
+static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, const T* in, T* out,
+                          hipStream_t s, const int* stop) {
+    unsigned* prog = F.prog + (backward ? F.nlines : 0);
+    unsigned* tick = F.ticket + (backward ? 1 : 0);
+    hipLaunchKernelGGL(reset_kernel, dim3(std::min(1024, (F.nlines + 255) / 256 + 1)), dim3(256), 0, s, prog,
+                       F.nlines);
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, tick, 1);
+    LGP_CHECK_LAUNCH();
+    const int64_t n = F.n;
+    if (F.d == 2) {
+        auto kf = backward ? sweep_kernel<T, 64, true, true> : sweep_kernel<T, 64, false, false>;
+        const int grid = persistent_grid((const void*)kf, 64, 0, F.nlines);
+        hipLaunchKernelGGL(kf, dim3(grid), dim3(64), 0, s, F.d, F.n1, n, F.nlo, (const int4*)F.d_offs,
+                           (const int*)F.line_order, F.nlines, F.Hx, F.Hy, A, scale, in, out, prog, tick,
+                           stop);
+    } else {
+        auto kf = backward ? sweep_kernel<T, 256, true, true> : sweep_kernel<T, 256, false, false>;
+        const int grid = persistent_grid((const void*)kf, 256, 0, F.nlines);
+        hipLaunchKernelGGL(kf, dim3(grid), dim3(256), 0, s, F.d, F.n1, n, F.nlo, (const int4*)F.d_offs,
+                           (const int*)F.line_order, F.nlines, F.Hx, F.Hy, A, scale, in, out, prog, tick,
+                           stop);
+    }
+    LGP_CHECK_LAUNCH();
+    return LGP_OK;
+}
+
+lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStream_t s, const int* stop) {
+    return backward ? sweep_t<double>(F, true, F.Ut, F.invD, in, out, s, stop)
+                    : sweep_t<double>(F, false, F.L, nullptr, in, out, s, stop);
+}
+
+lgp_status sweep32(Factor& F, bool backward, const float* in, float* out, hipStream_t s, const int* stop) {
+    if (!F.has32) return LGP_E_ARG;
+    return backward ? sweep_t<float>(F, true, F.Ut32, F.invD32, in, out, s, stop)
+                    : sweep_t<float>(F, false, F.L32, nullptr, in, out, s, stop);
+}
+
+}  // namespace lgp

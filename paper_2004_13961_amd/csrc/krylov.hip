@@ -1,0 +1,404 @@
+// PCG (paper Alg. 1) with device-resident scalars, and the FP64 iterative
+// refinement around a low-precision inner PCG.
+//
+// One iteration enqueues: z = U^{-1} L^{-1} r (two sweeps), rho = r.z,
+// p = z + (rho/rho_old) p, w = K p, alpha = rho / p.w, x += alpha p,
+// r -= alpha w, ||r||^2. Dot products are two-pass (fixed block partials,
+// then one block sums them in a fixed order), so results do not depend on
+// scheduling. Every kernel first reads the `done` flag and returns when a
+// previous step declared convergence or breakdown, so the host may enqueue
+// several iterations before it looks at the flag.
+#include <cmath>
+
+#include "lgp_internal.h"
+
+namespace lgp {
+
+constexpr int NPART = 512;     // partial sums per dot product
+constexpr int VBS = 256;
+
+enum {
+    SC_RHO = 0, SC_RHO_OLD, SC_PW, SC_RR, SC_ALPHA, SC_BETA, SC_FF, SC_THRESH2,
+    SC_K, SC_KMAX, SC_COUNT = 16
+};
+enum { FL_DONE = 0, FL_BREAK = 1, FL_FIRST = 2, FL_COUNT = 4 };
+
+struct SolveWS {
+    double* r; double* z; double* p; double* w;            // FP64
+    float* r32; float* z32; float* p32; float* w32; float* e32; float* y32;
+    double* part; double* sc; int* fl;
+    size_t bytes;
+};
+
+static size_t plan_ws(SolveWS& S, int64_t n, bool mixed, void* buf) {
+    Carver c(buf);
+    S.r = c.take<double>(n);
+    S.z = c.take<double>(n);
+    S.p = c.take<double>(n);
+    S.w = c.take<double>(n);
+    if (mixed) {
+        S.r32 = c.take<float>(n);
+        S.z32 = c.take<float>(n);
+        S.p32 = c.take<float>(n);
+        S.w32 = c.take<float>(n);
+        S.e32 = c.take<float>(n);
+        S.y32 = c.take<float>(n);
+    } else {
+        S.r32 = S.z32 = S.p32 = S.w32 = S.e32 = S.y32 = nullptr;
+    }
+    S.part = c.take<double>(NPART);
+    S.sc = c.take<double>(SC_COUNT);
+    S.fl = c.take<int>(FL_COUNT);
+    S.bytes = c.off + 256;
+    return S.bytes;
+}
+
+size_t solve_ws_bytes(int64_t n, bool mixed) {
+    SolveWS S;
+    return plan_ws(S, n, mixed, nullptr);
+}
+
+// ------------------------------------------------------------ kernels ----
+__device__ inline double block_sum(double v) {
+    __shared__ double red[VBS / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < VBS / 64; ++k) s += red[k];
+    __syncthreads();
+    return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(VBS) void dot_kernel(int64_t n, const T* __restrict__ a, const T* __restrict__ b,
+                                                  double* __restrict__ part, const int* __restrict__ fl) {
+    if (fl[FL_DONE]) return;
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VBS + threadIdx.x; i < n; i += (int64_t)NPART * VBS)
+        s += (double)a[i] * (double)b[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__device__ inline double sum_parts(const double* part) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < NPART; k += VBS) s += part[k];
+    return block_sum(s);
+}
+
+// rho_old = rho; rho = r.z; beta = rho/rho_old (0 on the first iteration)
+__global__ __launch_bounds__(VBS) void fin_rho_kernel(const double* part, double* sc, int* fl) {
+    if (fl[FL_DONE]) return;
+    const double s = sum_parts(part);
+    if (threadIdx.x == 0) {
+        sc[SC_RHO_OLD] = sc[SC_RHO];
+        sc[SC_RHO] = s;
+        if (fl[FL_FIRST]) sc[SC_BETA] = 0.0;
+        else sc[SC_BETA] = s / sc[SC_RHO_OLD];
+        if (!(s > 0.0) || !isfinite(s)) { fl[FL_BREAK] = 1; fl[FL_DONE] = 1; }
+    }
+}
+
+// alpha = rho / p.w
+__global__ __launch_bounds__(VBS) void fin_alpha_kernel(const double* part, double* sc, int* fl) {
+    if (fl[FL_DONE]) return;
+    const double s = sum_parts(part);
+    if (threadIdx.x == 0) {
+        sc[SC_PW] = s;
+        sc[SC_ALPHA] = sc[SC_RHO] / s;
+        if (!(s > 0.0) || !isfinite(s)) { fl[FL_BREAK] = 1; fl[FL_DONE] = 1; }
+    }
+}
+
+// rr = r.r; k += 1; stop when sqrt(rr) <= eps ||F|| or k >= k_max (Alg. 1)
+__global__ __launch_bounds__(VBS) void fin_rr_kernel(const double* part, double* sc, int* fl, int count_iter) {
+    if (fl[FL_DONE]) return;
+    const double s = sum_parts(part);
+    if (threadIdx.x == 0) {
+        sc[SC_RR] = s;
+        if (count_iter) {
+            sc[SC_K] += 1.0;
+            fl[FL_FIRST] = 0;
+        }
+        if (s <= sc[SC_THRESH2] || sc[SC_K] >= sc[SC_KMAX]) fl[FL_DONE] = 1;
+        if (!isfinite(s)) { fl[FL_BREAK] = 1; fl[FL_DONE] = 1; }
+    }
+}
+
+__global__ void fin_ff_kernel(const double* part, double* sc, double eps2) {
+    const double s = sum_parts(part);
+    if (threadIdx.x == 0) {
+        sc[SC_FF] = s;
+        sc[SC_THRESH2] = eps2 * s;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(VBS) void update_p_kernel(int64_t n, const T* __restrict__ z, T* __restrict__ p,
+                                                       const double* __restrict__ sc, const int* __restrict__ fl) {
+    if (fl[FL_DONE]) return;
+    const bool first = fl[FL_FIRST] != 0;
+    const T beta = (T)sc[SC_BETA];
+    for (int64_t i = blockIdx.x * (int64_t)VBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBS)
+        p[i] = first ? z[i] : z[i] + beta * p[i];
+}
+
+// x += alpha p; r -= alpha w; partial r.r
+template <typename T>
+__global__ __launch_bounds__(VBS) void update_xr_kernel(int64_t n, T* __restrict__ x, T* __restrict__ r,
+                                                        const T* __restrict__ p, const T* __restrict__ w,
+                                                        const double* __restrict__ sc, double* __restrict__ part,
+                                                        const int* __restrict__ fl) {
+    if (fl[FL_DONE]) return;
+    const T alpha = (T)sc[SC_ALPHA];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VBS + threadIdx.x; i < n; i += (int64_t)NPART * VBS) {
+        x[i] += alpha * p[i];
+        const T ri = r[i] - alpha * w[i];
+        r[i] = ri;
+        s += (double)ri * (double)ri;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// r = F - w
+__global__ void residual_kernel(int64_t n, const double* __restrict__ F, const double* __restrict__ w,
+                                double* __restrict__ r) {
+    for (int64_t i = blockIdx.x * (int64_t)VBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBS)
+        r[i] = F[i] - w[i];
+}
+
+// r32 = r * scale ; e32 = 0
+__global__ void to_inner_kernel(int64_t n, const double* __restrict__ r, float* __restrict__ r32,
+                                float* __restrict__ e32, double scale) {
+    for (int64_t i = blockIdx.x * (int64_t)VBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBS) {
+        r32[i] = (float)(r[i] * scale);
+        e32[i] = 0.f;
+    }
+}
+
+// x += scale e32
+__global__ void refine_kernel(int64_t n, double* __restrict__ x, const float* __restrict__ e32, double scale) {
+    for (int64_t i = blockIdx.x * (int64_t)VBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBS)
+        x[i] += scale * (double)e32[i];
+}
+
+__global__ void init_scalars_kernel(double* sc, int* fl, double kmax, double ff, double thresh2) {
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < SC_COUNT; ++k) sc[k] = 0.0;
+        sc[SC_KMAX] = kmax;
+        sc[SC_FF] = ff;
+        sc[SC_THRESH2] = thresh2;
+        fl[FL_DONE] = 0;
+        fl[FL_BREAK] = 0;
+        fl[FL_FIRST] = 1;
+        fl[3] = 0;
+    }
+}
+
+// restart: keep k, clear done, mark first iteration
+__global__ void restart_kernel(int* fl) {
+    if (threadIdx.x == 0) {
+        fl[FL_DONE] = 0;
+        fl[FL_BREAK] = 0;
+        fl[FL_FIRST] = 1;
+    }
+}
+
+static inline int vgrid(int64_t n) {
+    int64_t g = (n + VBS - 1) / VBS;
+    return (int)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
+// -------------------------------------------------------------- host -----
+struct HostState {
+    double sc[SC_COUNT];
+    int fl[FL_COUNT];
+};
+
+static lgp_status read_state(const SolveWS& S, hipStream_t s, HostState& h) {
+    LGP_HIP(hipMemcpyAsync(h.sc, S.sc, sizeof(h.sc), hipMemcpyDeviceToHost, s));
+    LGP_HIP(hipMemcpyAsync(h.fl, S.fl, sizeof(h.fl), hipMemcpyDeviceToHost, s));
+    LGP_HIP(hipStreamSynchronize(s));
+    return LGP_OK;
+}
+
+// Inner or outer PCG loop on vectors of type T. `mv` computes w = K p.
+template <typename T, typename MV, typename PC>
+static lgp_status pcg_loop(int64_t n, T* x, T* r, T* z, T* p, T* w, SolveWS& S, int max_iter, int check_every,
+                           MV mv, PC pc, hipStream_t s, int* iters_out, double* rr_out) {
+    HostState h;
+    lgp_status st;
+    for (;;) {
+        for (int it = 0; it < check_every; ++it) {
+            if ((st = pc(r, z)) != LGP_OK) return st;
+            hipLaunchKernelGGL(dot_kernel<T>, dim3(NPART), dim3(VBS), 0, s, n, (const T*)r, (const T*)z, S.part,
+                               (const int*)S.fl);
+            hipLaunchKernelGGL(fin_rho_kernel, dim3(1), dim3(VBS), 0, s, (const double*)S.part, S.sc, S.fl);
+            hipLaunchKernelGGL(update_p_kernel<T>, dim3(vgrid(n)), dim3(VBS), 0, s, n, (const T*)z, p,
+                               (const double*)S.sc, (const int*)S.fl);
+            if ((st = mv(p, w)) != LGP_OK) return st;   // kernels return early once done
+            hipLaunchKernelGGL(dot_kernel<T>, dim3(NPART), dim3(VBS), 0, s, n, (const T*)p, (const T*)w, S.part,
+                               (const int*)S.fl);
+            hipLaunchKernelGGL(fin_alpha_kernel, dim3(1), dim3(VBS), 0, s, (const double*)S.part, S.sc, S.fl);
+            hipLaunchKernelGGL(update_xr_kernel<T>, dim3(NPART), dim3(VBS), 0, s, n, x, r, (const T*)p, (const T*)w,
+                               (const double*)S.sc, S.part, (const int*)S.fl);
+            hipLaunchKernelGGL(fin_rr_kernel, dim3(1), dim3(VBS), 0, s, (const double*)S.part, S.sc, S.fl, 1);
+            LGP_CHECK_LAUNCH();
+        }
+        if ((st = read_state(S, s, h)) != LGP_OK) return st;
+        if (h.fl[FL_DONE]) break;
+        if ((int)h.sc[SC_K] >= max_iter) break;
+    }
+    *iters_out = (int)h.sc[SC_K];
+    *rr_out = h.sc[SC_RR];
+    if (h.fl[FL_BREAK]) return LGP_E_BREAKDOWN;
+    return LGP_OK;
+}
+
+// ||F||^2 into sc[SC_FF], threshold eps^2 ||F||^2
+static lgp_status norm2_into(const double* v, int64_t n, SolveWS& S, double eps, hipStream_t s) {
+    hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, s, S.sc, S.fl, 0.0, 0.0, 0.0);
+    hipLaunchKernelGGL(dot_kernel<double>, dim3(NPART), dim3(VBS), 0, s, n, v, v, S.part, (const int*)S.fl);
+    hipLaunchKernelGGL(fin_ff_kernel, dim3(1), dim3(VBS), 0, s, (const double*)S.part, S.sc, eps * eps);
+    LGP_CHECK_LAUNCH();
+    return LGP_OK;
+}
+
+lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, const lgp_solve_opts& o, void* ws,
+                          size_t ws_bytes, hipStream_t s, lgp_solve_info* info) {
+    const int64_t n = P.n;
+    const bool mixed = (o.inner != LGP_F64);
+    SolveWS S;
+    if (plan_ws(S, n, mixed, ws) > ws_bytes) return LGP_E_NOMEM;
+    if (mixed && !M.has32) return LGP_E_ARG;
+    lgp_status st;
+    info->iters = 0;
+    info->outer = 0;
+    info->relres_true = NAN;
+    info->relres_recursive = NAN;
+    info->status = LGP_OK;
+    HostState h;
+
+    // ||F||
+    if ((st = norm2_into(F, n, S, o.rtol, s)) != LGP_OK) return st;
+    if ((st = read_state(S, s, h)) != LGP_OK) return st;
+    const double normF = sqrt(h.sc[SC_FF]);
+    if (!(normF > 0.0)) {
+        // F = 0: x = 0 is the solution
+        LGP_HIP(hipMemsetAsync(x, 0, n * 8, s));
+        LGP_HIP(hipStreamSynchronize(s));
+        info->relres_true = 0.0;
+        info->relres_recursive = 0.0;
+        return LGP_OK;
+    }
+    auto true_residual = [&](double* relres) -> lgp_status {
+        lgp_status st2;
+        if ((st2 = matvec_f64(P, x, S.w, s)) != LGP_OK) return st2;
+        hipLaunchKernelGGL(residual_kernel, dim3(vgrid(n)), dim3(VBS), 0, s, n, F, (const double*)S.w, S.r);
+        hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, s, S.sc, S.fl, 0.0, 0.0, 0.0);
+        hipLaunchKernelGGL(dot_kernel<double>, dim3(NPART), dim3(VBS), 0, s, n, (const double*)S.r,
+                           (const double*)S.r, S.part, (const int*)S.fl);
+        hipLaunchKernelGGL(fin_ff_kernel, dim3(1), dim3(VBS), 0, s, (const double*)S.part, S.sc, 0.0);
+        LGP_CHECK_LAUNCH();
+        HostState h2;
+        if ((st2 = read_state(S, s, h2)) != LGP_OK) return st2;
+        *relres = sqrt(h2.sc[SC_FF]) / normF;
+        return LGP_OK;
+    };
+
+    double relres = 0.0;
+    if ((st = true_residual(&relres)) != LGP_OK) return st;
+    const int check_every = o.check_every > 0 ? o.check_every : 4;
+
+    if (!mixed) {
+        int restarts = 0;
+        int total = 0;
+        double rr = 0.0;
+        while (relres > o.rtol) {
+            if (total >= o.max_iter || restarts > 3) break;
+            // fresh scalars; r already = F - K x
+            // fresh scalars; the stop rule uses ||F||, not ||r0|| (Alg. 1)
+            hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, s, S.sc, S.fl,
+                               (double)(o.max_iter - total), normF * normF, o.rtol * o.rtol * normF * normF);
+            LGP_CHECK_LAUNCH();
+            int it = 0;
+            st = pcg_loop<double>(
+                n, x, S.r, S.z, S.p, S.w, S, o.max_iter - total, check_every,
+                [&](const double* pp, double* ww) { return matvec_f64(P, pp, ww, s); },
+                [&](const double* rr_, double* zz) {
+                    lgp_status a = sweep(M, false, rr_, M.y_tmp, s, S.fl);
+                    if (a != LGP_OK) return a;
+                    return sweep(M, true, M.y_tmp, zz, s, S.fl);
+                },
+                s, &it, &rr);
+            total += it;
+            if (st != LGP_OK) {
+                info->iters = total;
+                info->status = st;
+                return st;
+            }
+            lgp_status st2 = true_residual(&relres);
+            if (st2 != LGP_OK) return st2;
+            info->relres_recursive = sqrt(rr) / normF;
+            if (relres > o.rtol) ++restarts;
+        }
+        info->iters = total;
+        info->outer = restarts;
+        info->relres_true = relres;
+        if (relres > o.rtol) {
+            info->status = LGP_E_NOCONV;
+            return LGP_E_NOCONV;
+        }
+        return LGP_OK;
+    }
+
+    // mixed precision: FP64 iterative refinement around an inner PCG
+    const GemmMode mode = (o.inner == LGP_BF16) ? GEMM_BF16 : GEMM_F32;
+    int outer = 0, total = 0;
+    while (relres > o.rtol && outer < o.max_outer && total < o.max_iter) {
+        // S.r holds F - K x (from true_residual); its norm^2 is in sc[SC_FF]
+        const double rnorm = relres * normF;
+        hipLaunchKernelGGL(to_inner_kernel, dim3(vgrid(n)), dim3(VBS), 0, s, n, (const double*)S.r, S.r32, S.e32,
+                           1.0 / rnorm);
+        // the inner right-hand side has unit norm
+        hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, s, S.sc, S.fl, (double)(o.max_iter - total),
+                           1.0, o.inner_rtol * o.inner_rtol);
+        LGP_CHECK_LAUNCH();
+        int it = 0;
+        double rr = 0.0;
+        st = pcg_loop<float>(
+            n, S.e32, S.r32, S.z32, S.p32, S.w32, S, o.max_iter - total, check_every,
+            [&](const float* pp, float* ww) { return matvec_lp(P, pp, ww, mode, s); },
+            [&](const float* rr_, float* zz) {
+                lgp_status a = sweep32(M, false, rr_, S.y32, s, S.fl);
+                if (a != LGP_OK) return a;
+                return sweep32(M, true, S.y32, zz, s, S.fl);
+            },
+            s, &it, &rr);
+        total += it;
+        if (st != LGP_OK && st != LGP_E_BREAKDOWN) return st;
+        // x += |r| e
+        hipLaunchKernelGGL(refine_kernel, dim3(vgrid(n)), dim3(VBS), 0, s, n, x, (const float*)S.e32, rnorm);
+        LGP_CHECK_LAUNCH();
+        ++outer;
+        lgp_status st2 = true_residual(&relres);
+        if (st2 != LGP_OK) return st2;
+        info->relres_recursive = sqrt(rr);
+        if (it == 0) break;   // inner solver made no progress
+    }
+    info->iters = total;
+    info->outer = outer;
+    info->relres_true = relres;
+    if (relres > o.rtol) {
+        info->status = LGP_E_NOCONV;
+        return LGP_E_NOCONV;
+    }
+    return LGP_OK;
+}
+
+}  // namespace lgp

@@ -1,0 +1,141 @@
+// Internal declarations shared by the HIP translation units of liblgpcg.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+#include <vector>
+
+#include "../../include/lgpcg.h"
+
+namespace lgp {
+
+extern thread_local int g_last_hip_error;
+
+#define LGP_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) {                                         \
+            ::lgp::g_last_hip_error = (int)e_;                          \
+            return LGP_E_HIP;                                           \
+        }                                                               \
+    } while (0)
+
+#define LGP_CHECK_LAUNCH()                                              \
+    do {                                                                \
+        hipError_t e_ = hipGetLastError();                              \
+        if (e_ != hipSuccess) {                                         \
+            ::lgp::g_last_hip_error = (int)e_;                          \
+            return LGP_E_HIP;                                           \
+        }                                                               \
+    } while (0)
+
+// Bump allocator over a caller-provided device buffer (256-byte aligned
+// sub-buffers). Used twice: once with base == nullptr to size, once to carve.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// ------------------------------------------------------------- GEMM ------
+// C[b](i,j) (+)= E[b](i,j) * sum_k A[b](i,k) B[b](k,j), element addresses via
+// strides (in elements). E may be null (no epilogue multiply).
+enum GemmMode { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2 };
+
+struct GemmArgs {
+    const void* A; int64_t sAb, sAi, sAk;
+    const void* B; int64_t sBb, sBk, sBj;
+    void* C;       int64_t sCb, sCi, sCj;
+    const void* E; int64_t sEb, sEi, sEj;
+    int M, N, K, batch;
+    int accumulate;
+};
+
+lgp_status gemm(GemmMode mode, const GemmArgs& g, hipStream_t s);
+
+// ----------------------------------------------------------- problem -----
+struct Problem {
+    int d, N, n1, q;
+    int64_t n, nq;            // (N-1)^d, (N+1)^d
+    std::vector<double> x, w; // host nodes / weights
+    // device tables (FP64)
+    double* PDT;    // [n1][2q]  : [Phi^T | D^T]          (PDT[k][m] = Phi[m][k], PDT[k][q+m] = D[m][k])
+    double* PhiD;   // [2q][n1]  : [Phi ; D]
+    double* DP;     // [2q][n1]  : [D ; Phi]
+    double* Wnodes; // [nq] tensor weights
+    double* wab;    // [2][nq]   : W*b then W*a
+    double* a_nodes;// [nq]  copy of a
+    double* b_nodes;// [nq]  copy of b
+    // FP32 copies for the low-precision matvec
+    float* PDT32; float* PhiD32; float* DP32; float* wab32;
+    // matvec scratch (sized for the largest stage), FP64 and FP32 views share it
+    double* s0; double* s1; double* s2; double* s3;
+    size_t s0n, s1n, s2n, s3n;
+    int* flag;      // device status flag
+    size_t bytes;
+};
+
+size_t plan_problem(Problem& P, void* buf);
+lgp_status matvec_f64(Problem& P, const double* u, double* y, hipStream_t s);
+lgp_status matvec_lp(Problem& P, const float* u, float* y, GemmMode mode, hipStream_t s);
+lgp_status load_vector(Problem& P, const double* f, double* F, hipStream_t s);
+
+// ------------------------------------------------------------ factor -----
+struct Factor {
+    Problem* P;
+    int d, n1, Ta, Tb, T, h;   // h = reach of the pattern per direction
+    int64_t n;
+    int noff, nlo;             // pattern size, number of strictly lower offsets
+    std::vector<int> offs;     // host, 3*noff
+    int Hx, Hy, Hz;            // max |offset| per direction
+    int nlines;                // lines of constant (y,z)
+    int levels;
+    // device
+    double* L;        // [n][nlo]
+    double* Ut;       // [n][nlo]  backward-sweep operator in reversed order
+    double* Dg;       // [n] pivots
+    double* invD;     // [n]
+    float* L32; float* Ut32; float* invD32;   // optional FP32 copies
+    int* d_offs;      // [nlo][4] (dx,dy,dz,linear)
+    int* line_order;  // [nlines] line ids in dependency order
+    unsigned* prog;   // [2][nlines] progress counters (fwd, bwd)
+    unsigned* ticket; // [4]
+    int* flag;        // [4] device flags
+    double* coefA;    // [(T+1)^d] truncated coefficients of a (x fastest)
+    double* coefB;    // [(T+1)^d]
+    double* band;     // [2][T+1][n1][2h+1]  S^(t)(i, i+delta), M^(t)(i, i+delta)
+    int* pair_ptr;    // [nlo+1]  CSR over k: rows j > k with offset(k)-offset(j) lower
+    int* pair_j;      // [npairs] j index (lower offset index, or nlo for the diagonal)
+    int* pair_l;      // [npairs] index of offset(k) - offset(j) in the lower list
+    int npairs;
+    double* y_tmp;    // [n] intermediate of precond_apply
+    bool has32;
+    size_t bytes;
+};
+
+size_t plan_factor(Factor& F, void* buf, bool with32);
+lgp_status factor_build(Factor& F, hipStream_t s);
+lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStream_t s,
+                 const int* stop = nullptr);
+lgp_status sweep32(Factor& F, bool backward, const float* in, float* out, hipStream_t s,
+                   const int* stop = nullptr);
+
+// PCG driver
+size_t solve_ws_bytes(int64_t n, bool mixed);
+lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, const lgp_solve_opts& o, void* ws,
+                          size_t ws_bytes, hipStream_t s, lgp_solve_info* info);
+lgp_status build_tables(Problem& P, hipStream_t s);
+lgp_status setup_nodes(Problem& P, const double* a, const double* b, hipStream_t s, bool* coef_ok);
+
+// host helpers
+void gauss_legendre_host(int N, std::vector<double>& x, std::vector<double>& w);
+double triple_legendre(int t, int m, int n);   // int L_t L_m L_n over (-1,1)
+
+}  // namespace lgp

@@ -1,0 +1,303 @@
+// Problem setup and the sum-factorised operator K = A + B (paper Sec. 4.3).
+//
+// Steps 1-2 of the fast product (compact-basis coefficients -> values and
+// derivatives at the Legendre-Gauss nodes) and steps 3-4 (pointwise
+// multiply by W*a, W*b, then the transposed maps back, which is the FDLT
+// followed by the step-4 recombination) are folded into 1D tables
+//     Phi[m][k] = phi_k(x_m) = L_k(x_m) - L_{k+2}(x_m)
+//     D[m][k]   = phi_k'(x_m) = -(2k+3) L_{k+1}(x_m)   (derivative relation)
+// applied direction by direction as matrix-core contractions (gemm.hip).
+// W is the tensor Gauss weight, so sum_nodes W g v is exactly (I_N g, v).
+#include <cmath>
+
+#include "lgp_internal.h"
+
+namespace lgp {
+
+thread_local int g_last_hip_error = 0;
+
+// Newton on the three-term recurrence in extended precision; symmetric nodes
+// are mirrored so x_i = -x_{N-i} exactly.
+void gauss_legendre_host(int N, std::vector<double>& x, std::vector<double>& w) {
+    const int m = N + 1;
+    x.assign(m, 0.0);
+    w.assign(m, 0.0);
+    for (int i = 0; i < (m + 1) / 2; ++i) {
+        long double z = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (m + 0.5L));
+        long double dp = 1.0L;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1.0L, p1 = z;
+            for (int k = 1; k < m; ++k) {
+                long double p2 = ((2 * k + 1) * z * p1 - k * p0) / (k + 1);
+                p0 = p1;
+                p1 = p2;
+            }
+            // p1 = L_m(z), p0 = L_{m-1}(z); (1-z^2) L_m' = m (L_{m-1} - z L_m)
+            dp = m * (p0 - z * p1) / (1.0L - z * z);
+            long double dz = p1 / dp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        {
+            long double p0 = 1.0L, p1 = z;
+            for (int k = 1; k < m; ++k) {
+                long double p2 = ((2 * k + 1) * z * p1 - k * p0) / (k + 1);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = m * (p0 - z * p1) / (1.0L - z * z);
+        }
+        const long double wt = 2.0L / ((1.0L - z * z) * dp * dp);
+        // z is the i-th largest root
+        x[m - 1 - i] = (double)z;
+        x[i] = -(double)z;
+        w[m - 1 - i] = (double)wt;
+        w[i] = (double)wt;
+    }
+    if (m % 2 == 1) x[m / 2] = 0.0;
+}
+
+size_t plan_problem(Problem& P, void* buf) {
+    Carver c(buf);
+    const int n1 = P.n1, q = P.q;
+    const size_t tab = (size_t)n1 * 2 * q;
+    P.PDT = c.take<double>(tab);
+    P.PhiD = c.take<double>(tab);
+    P.DP = c.take<double>(tab);
+    P.Wnodes = c.take<double>(P.nq);
+    P.wab = c.take<double>(2 * P.nq);
+    P.a_nodes = c.take<double>(P.nq);
+    P.b_nodes = c.take<double>(P.nq);
+    P.PDT32 = c.take<float>(tab);
+    P.PhiD32 = c.take<float>(tab);
+    P.DP32 = c.take<float>(tab);
+    P.wab32 = c.take<float>(2 * P.nq);
+    if (P.d == 2) {
+        P.s0n = (size_t)n1 * 2 * q;
+        P.s1n = (size_t)2 * q * q;
+        P.s2n = (size_t)q * q;
+        P.s3n = (size_t)n1 * 2 * q;
+    } else {
+        P.s0n = (size_t)n1 * n1 * 2 * q;
+        P.s1n = (size_t)3 * n1 * q * q;
+        P.s2n = (size_t)4 * q * q * q;
+        P.s3n = (size_t)3 * n1 * q * q;
+    }
+    // room for the truncated-coefficient transforms of the preconditioner
+    // (degrees up to 24): FT table (25 x q) in s3, stage outputs in s0/s1/s2
+    {
+        const size_t T1 = 25;
+        const size_t q_ = (size_t)q;
+        const size_t st0 = (P.d == 2) ? q_ * T1 : q_ * q_ * T1;
+        const size_t st1 = (P.d == 2) ? 0 : q_ * T1 * T1;
+        const size_t st2 = (P.d == 2) ? T1 * T1 : T1 * T1 * T1;
+        if (P.s0n < st0) P.s0n = st0;
+        if (P.s1n < st1) P.s1n = st1;
+        if (P.s2n < st2) P.s2n = st2;
+        if (P.s3n < T1 * q_) P.s3n = T1 * q_;
+    }
+    P.s0 = c.take<double>(P.s0n);
+    P.s1 = c.take<double>(P.s1n);
+    P.s2 = c.take<double>(P.s2n);
+    P.s3 = c.take<double>(P.s3n);
+    P.flag = c.take<int>(4);
+    P.bytes = c.off + 256;
+    return P.bytes;
+}
+
+// ------------------------------------------------------------ kernels ----
+__global__ void node_setup_kernel(int d, int q, int64_t nq, const double* __restrict__ w1,
+                                  const double* __restrict__ a, const double* __restrict__ b,
+                                  double* __restrict__ W, double* __restrict__ wab,
+                                  float* __restrict__ wab32, int* flag) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nq;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = idx;
+        double wt = 1.0;
+        for (int k = 0; k < d; ++k) {
+            wt *= w1[r % q];
+            r /= q;
+        }
+        const double av = a[idx], bv = b[idx];
+        W[idx] = wt;
+        wab[idx] = wt * bv;
+        wab[nq + idx] = wt * av;
+        wab32[idx] = (float)(wt * bv);
+        wab32[nq + idx] = (float)(wt * av);
+        // model problem of Sec. 3: a > 0, b >= 0, both finite
+        if (!(av > 0.0) || !(bv >= 0.0) || !isfinite(av) || !isfinite(bv)) atomicOr(flag, 1);
+    }
+}
+
+__global__ void weight_kernel(int64_t nq, const double* __restrict__ W, const double* __restrict__ f,
+                              double* __restrict__ g) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nq;
+         idx += (int64_t)gridDim.x * blockDim.x)
+        g[idx] = W[idx] * f[idx];
+}
+
+static inline int grid_for(int64_t n, int bs = 256, int cap = 4096) {
+    int64_t g = (n + bs - 1) / bs;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// ------------------------------------------------------------- setup -----
+lgp_status build_tables(Problem& P, hipStream_t s) {
+    const int n1 = P.n1, q = P.q, N = P.N;
+    gauss_legendre_host(N, P.x, P.w);
+    const size_t tab = (size_t)n1 * 2 * q;
+    std::vector<double> PDT(tab), PhiD(tab), DP(tab);
+    std::vector<float> PDT32(tab), PhiD32(tab), DP32(tab);
+    std::vector<long double> L(N + 2);
+    for (int m = 0; m < q; ++m) {
+        const long double z = P.x[m];
+        L[0] = 1.0L;
+        L[1] = z;
+        for (int k = 1; k <= N; ++k) L[k + 1] = ((2 * k + 1) * z * L[k] - k * L[k - 1]) / (k + 1);
+        for (int k = 0; k < n1; ++k) {
+            const double phi = (double)(L[k] - L[k + 2]);
+            const double dphi = (double)(-(2 * k + 3) * L[k + 1]);
+            PDT[(size_t)k * 2 * q + m] = phi;
+            PDT[(size_t)k * 2 * q + q + m] = dphi;
+            PhiD[(size_t)m * n1 + k] = phi;
+            PhiD[(size_t)(q + m) * n1 + k] = dphi;
+            DP[(size_t)m * n1 + k] = dphi;
+            DP[(size_t)(q + m) * n1 + k] = phi;
+        }
+    }
+    for (size_t i = 0; i < tab; ++i) {
+        PDT32[i] = (float)PDT[i];
+        PhiD32[i] = (float)PhiD[i];
+        DP32[i] = (float)DP[i];
+    }
+    LGP_HIP(hipMemcpyAsync(P.PDT, PDT.data(), tab * 8, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(P.PhiD, PhiD.data(), tab * 8, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(P.DP, DP.data(), tab * 8, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(P.PDT32, PDT32.data(), tab * 4, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(P.PhiD32, PhiD32.data(), tab * 4, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(P.DP32, DP32.data(), tab * 4, hipMemcpyHostToDevice, s));
+    // the host vectors must stay alive until the copies finish
+    LGP_HIP(hipStreamSynchronize(s));
+    return LGP_OK;
+}
+
+lgp_status setup_nodes(Problem& P, const double* a, const double* b, hipStream_t s, bool* coef_ok) {
+    LGP_HIP(hipMemcpyAsync(P.a_nodes, a, P.nq * 8, hipMemcpyDeviceToDevice, s));
+    LGP_HIP(hipMemcpyAsync(P.b_nodes, b, P.nq * 8, hipMemcpyDeviceToDevice, s));
+    LGP_HIP(hipMemsetAsync(P.flag, 0, 4 * sizeof(int), s));
+    // the 1D weights ride in the first q doubles of scratch s2
+    LGP_HIP(hipMemcpyAsync(P.s2, P.w.data(), P.q * 8, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(node_setup_kernel, dim3(grid_for(P.nq)), dim3(256), 0, s, P.d, P.q, P.nq,
+                       (const double*)P.s2, P.a_nodes, P.b_nodes, P.Wnodes, P.wab, P.wab32, P.flag);
+    LGP_CHECK_LAUNCH();
+    int hflag = 0;
+    LGP_HIP(hipMemcpyAsync(&hflag, P.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    LGP_HIP(hipStreamSynchronize(s));
+    *coef_ok = (hflag == 0);
+    return LGP_OK;
+}
+
+// ------------------------------------------------------------ matvec -----
+// Element-generic driver: `es` = element size (8 for FP64, 4 otherwise).
+template <typename T>
+static lgp_status matvec_impl(Problem& P, const T* u, T* y, GemmMode mode, const T* PDT, const T* PhiD,
+                              const T* DP, const T* wab, hipStream_t s) {
+    const int n1 = P.n1, q = P.q;
+    const int64_t nq = P.nq;
+    T* s0 = (T*)P.s0;
+    T* s1 = (T*)P.s1;
+    T* s2 = (T*)P.s2;
+    T* s3 = (T*)P.s3;
+    lgp_status st;
+#define GEMM(...)                                   \
+    do {                                            \
+        GemmArgs g_ = __VA_ARGS__;                  \
+        if ((st = gemm(mode, g_, s)) != LGP_OK) return st; \
+    } while (0)
+    // GemmArgs field order:
+    // A,sAb,sAi,sAk, B,sBb,sBk,sBj, C,sCb,sCi,sCj, E,sEb,sEi,sEj, M,N,K,batch, accumulate
+    if (P.d == 2) {
+        // stage 1: T = U [Phi^T | D^T]                 (n1 x 2q)
+        GEMM({u, 0, n1, 1, PDT, 0, 2 * q, 1, s0, 0, 2 * q, 1, nullptr, 0, 0, 0, n1, 2 * q, n1, 1, 0});
+        // stage 2a: [g0; gy] = ([Phi; D] T1) .* [Wb; Wa]  (2q x q)
+        GEMM({PhiD, 0, n1, 1, s0, 0, 2 * q, 1, s1, 0, q, 1, wab, 0, q, 1, 2 * q, q, n1, 1, 0});
+        // stage 2b: gx = (Phi T2) .* Wa                    (q x q)
+        GEMM({PhiD, 0, n1, 1, s0 + q, 0, 2 * q, 1, s2, 0, q, 1, wab + nq, 0, q, 1, q, q, n1, 1, 0});
+        // stage 3a: Ax = Phi^T gx                          (n1 x q) -> s3[:, :q]
+        GEMM({PDT, 0, 2 * q, 1, s2, 0, q, 1, s3, 0, 2 * q, 1, nullptr, 0, 0, 0, n1, q, q, 1, 0});
+        // stage 3b: A0y = Phi^T g0 + D^T gy                (n1 x q) -> s3[:, q:]
+        GEMM({PDT, 0, 2 * q, 1, s1, 0, q, 1, s3 + q, 0, 2 * q, 1, nullptr, 0, 0, 0, n1, q, 2 * q, 1, 0});
+        // stage 4: Y = [Ax | A0y] [D; Phi]                 (n1 x n1)
+        GEMM({s3, 0, 2 * q, 1, DP, 0, n1, 1, y, 0, n1, 1, nullptr, 0, 0, 0, n1, n1, 2 * q, 1, 0});
+        return LGP_OK;
+    }
+    const int64_t n1q2 = (int64_t)n1 * 2 * q, qq = (int64_t)q * q, q3 = nq;
+    const int n1sq = n1 * n1;
+    // X1: T[iz,iy][c] = sum_ix U[iz,iy,ix] [Phi^T | D^T][ix][c]
+    GEMM({u, 0, n1, 1, PDT, 0, 2 * q, 1, s0, 0, 2 * q, 1, nullptr, 0, 0, 0, n1sq, 2 * q, n1, 1, 0});
+    // Y1a: R1[iz] = [Phi; D] Tphi[iz]      (2q x q per iz)
+    GEMM({PhiD, 0, n1, 1, s0, n1q2, 2 * q, 1, s1, 2 * qq, q, 1, nullptr, 0, 0, 0, 2 * q, q, n1, n1, 0});
+    // Y1b: R2[iz] = Phi Td[iz]              (q x q per iz)
+    T* R2 = s1 + (int64_t)n1 * 2 * qq;
+    GEMM({PhiD, 0, n1, 1, s0 + q, n1q2, 2 * q, 1, R2, qq, q, 1, nullptr, 0, 0, 0, q, q, n1, n1, 0});
+    // Z1a: [g0; gz] = ([Phi; D] over z applied to Tphiphi) .* [Wb; Wa]
+    GEMM({PhiD, 0, n1, 1, s1, 0, 2 * qq, 1, s2, 0, qq, 1, wab, 0, qq, 1, 2 * q, (int)qq, n1, 1, 0});
+    // Z1b: gy = (Phi_z Tdphi) .* Wa
+    GEMM({PhiD, 0, n1, 1, s1 + qq, 0, 2 * qq, 1, s2 + 2 * q3, 0, qq, 1, wab + nq, 0, qq, 1, q, (int)qq, n1, 1, 0});
+    // Z1c: gx = (Phi_z R2) .* Wa
+    GEMM({PhiD, 0, n1, 1, R2, 0, qq, 1, s2 + 3 * q3, 0, qq, 1, wab + nq, 0, qq, 1, q, (int)qq, n1, 1, 0});
+    // Z2a: Zb[iz][0] = Phi_z^T g0 + D_z^T gz
+    GEMM({PDT, 0, 2 * q, 1, s2, 0, qq, 1, s3, 0, 3 * qq, 1, nullptr, 0, 0, 0, n1, (int)qq, 2 * q, 1, 0});
+    // Z2b: Zb[iz][1] = Phi_z^T gy
+    GEMM({PDT, 0, 2 * q, 1, s2 + 2 * q3, 0, qq, 1, s3 + qq, 0, 3 * qq, 1, nullptr, 0, 0, 0, n1, (int)qq, q, 1, 0});
+    // Z2c: Zb[iz][2] = Phi_z^T gx
+    GEMM({PDT, 0, 2 * q, 1, s2 + 3 * q3, 0, qq, 1, s3 + 2 * qq, 0, 3 * qq, 1, nullptr, 0, 0, 0, n1, (int)qq, q, 1, 0});
+    // Y2a: Cbuf[iz][:, q:] = Phi_y^T Zb[iz][0] + D_y^T Zb[iz][1]
+    GEMM({PDT, 0, 2 * q, 1, s3, 3 * qq, q, 1, s0 + q, n1q2, 2 * q, 1, nullptr, 0, 0, 0, n1, q, 2 * q, n1, 0});
+    // Y2b: Cbuf[iz][:, :q] = Phi_y^T Zb[iz][2]
+    GEMM({PDT, 0, 2 * q, 1, s3 + 2 * qq, 3 * qq, q, 1, s0, n1q2, 2 * q, 1, nullptr, 0, 0, 0, n1, q, q, n1, 0});
+    // X2: Y = Cbuf [D; Phi]
+    GEMM({s0, 0, 2 * q, 1, DP, 0, n1, 1, y, 0, n1, 1, nullptr, 0, 0, 0, n1sq, n1, 2 * q, 1, 0});
+#undef GEMM
+    return LGP_OK;
+}
+
+lgp_status matvec_f64(Problem& P, const double* u, double* y, hipStream_t s) {
+    return matvec_impl<double>(P, u, y, GEMM_F64, P.PDT, P.PhiD, P.DP, P.wab, s);
+}
+
+lgp_status matvec_lp(Problem& P, const float* u, float* y, GemmMode mode, hipStream_t s) {
+    return matvec_impl<float>(P, u, y, mode, P.PDT32, P.PhiD32, P.DP32, P.wab32, s);
+}
+
+lgp_status load_vector(Problem& P, const double* f, double* F, hipStream_t s) {
+    const int n1 = P.n1, q = P.q;
+    const int64_t qq = (int64_t)q * q;
+    lgp_status st;
+    hipLaunchKernelGGL(weight_kernel, dim3(grid_for(P.nq)), dim3(256), 0, s, P.nq, P.Wnodes, f, P.s2);
+    LGP_CHECK_LAUNCH();
+    const double* Phi = P.DP + (int64_t)q * n1;   // rows q..2q-1 of [D; Phi]
+#define GEMM(...)                                                   \
+    do {                                                            \
+        GemmArgs g_ = __VA_ARGS__;                                  \
+        if ((st = gemm(GEMM_F64, g_, s)) != LGP_OK) return st;      \
+    } while (0)
+    if (P.d == 2) {
+        // A = Phi^T g (n1 x q), F = A Phi (n1 x n1)
+        GEMM({P.PDT, 0, 2 * q, 1, P.s2, 0, q, 1, P.s3, 0, q, 1, nullptr, 0, 0, 0, n1, q, q, 1, 0});
+        GEMM({P.s3, 0, q, 1, Phi, 0, n1, 1, F, 0, n1, 1, nullptr, 0, 0, 0, n1, n1, q, 1, 0});
+        return LGP_OK;
+    }
+    // z: (n1 x q^2) = Phi^T g
+    GEMM({P.PDT, 0, 2 * q, 1, P.s2, 0, qq, 1, P.s3, 0, qq, 1, nullptr, 0, 0, 0, n1, (int)qq, q, 1, 0});
+    // y: per iz (n1 x q) = Phi^T s3[iz]
+    GEMM({P.PDT, 0, 2 * q, 1, P.s3, qq, q, 1, P.s0, (int64_t)n1 * q, q, 1, nullptr, 0, 0, 0, n1, q, q, n1, 0});
+    // x: F (n1^2 x n1) = s0 Phi
+    GEMM({P.s0, 0, q, 1, Phi, 0, n1, 1, F, 0, n1, 1, nullptr, 0, 0, 0, n1 * n1, n1, q, 1, 0});
+#undef GEMM
+    return LGP_OK;
+}
+
+}  // namespace lgp

@@ -1,0 +1,151 @@
+"""Python objects over the C ABI: Problem, Factor and pcg_solve.
+
+Device buffers are torch uint8 tensors sized by the library's queries; the
+stream is torch's current stream. Tensors passed in must be contiguous CUDA
+tensors of the documented dtype and length.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import lgpcg
+from .lgpcg import DTYPES, check, lib
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, numel: int, name: str):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.numel() == numel):
+        raise ValueError("%s must be a contiguous CUDA %s tensor with %d elements" % (name, dtype, numel))
+
+
+class Problem:
+    """The operator K = A + B for nodal coefficients a, b on the (N+1)^d
+    Legendre-Gauss grid (x fastest)."""
+
+    def __init__(self, d: int, N: int, a_nodes: torch.Tensor, b_nodes: torch.Tensor):
+        L = lib()
+        self.d, self.N = d, N
+        self.n1, self.q = N - 1, N + 1
+        self.n = self.n1 ** d
+        self.nq = self.q ** d
+        _need(a_nodes, torch.float64, self.nq, "a_nodes")
+        _need(b_nodes, torch.float64, self.nq, "b_nodes")
+        nbytes = L.lgp_problem_bytes(d, N)
+        if nbytes == 0:
+            raise lgpcg.LgpError(1, "lgp_problem_bytes")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        check(L.lgp_build_problem(d, N, _ptr(a_nodes), _ptr(b_nodes), _ptr(self.buf), nbytes, _stream(),
+                                  ctypes.byref(h)), "lgp_build_problem")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and lgpcg._lib is not None:
+            lgpcg._lib.lgp_destroy_problem(h)
+            self.handle = None
+
+    def matvec(self, u: torch.Tensor, y: torch.Tensor = None, prec: str = "f64") -> torch.Tensor:
+        dt = torch.float64 if prec == "f64" else torch.float32
+        _need(u, dt, self.n, "u")
+        if y is None:
+            y = torch.empty_like(u)
+        _need(y, dt, self.n, "y")
+        check(lib().lgp_matvec(self.handle, _ptr(u), _ptr(y), DTYPES[prec], _stream()), "lgp_matvec")
+        return y
+
+    def load_vector(self, f_nodes: torch.Tensor, F: torch.Tensor = None) -> torch.Tensor:
+        _need(f_nodes, torch.float64, self.nq, "f_nodes")
+        if F is None:
+            F = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        check(lib().lgp_load_vector(self.handle, _ptr(f_nodes), _ptr(F), _stream()), "lgp_load_vector")
+        return F
+
+
+class Factor:
+    """ILU(0) factors of the preconditioner M (truncations Ta for a, Tb for b)."""
+
+    def __init__(self, problem: Problem, Ta: int, Tb: int = None, store: str = "f64"):
+        L = lib()
+        Tb = Ta if Tb is None else Tb
+        self.problem = problem
+        self.Ta, self.Tb = Ta, Tb
+        nbytes = L.lgp_factor_bytes(problem.handle, Ta, Tb, DTYPES[store])
+        if nbytes == 0:
+            raise lgpcg.LgpError(1, "lgp_factor_bytes")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        check(L.lgp_factor_M(problem.handle, Ta, Tb, DTYPES[store], _ptr(self.buf), nbytes, _stream(),
+                             ctypes.byref(h)), "lgp_factor_M")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and lgpcg._lib is not None:
+            lgpcg._lib.lgp_destroy_factor(h)
+            self.handle = None
+
+    def _vec(self, v, name):
+        _need(v, torch.float64, self.problem.n, name)
+
+    def apply(self, r: torch.Tensor, z: torch.Tensor = None) -> torch.Tensor:
+        self._vec(r, "r")
+        z = torch.empty_like(r) if z is None else z
+        check(lib().lgp_precond_apply(self.handle, _ptr(r), _ptr(z), _stream()), "lgp_precond_apply")
+        return z
+
+    def forward(self, r: torch.Tensor, y: torch.Tensor = None) -> torch.Tensor:
+        self._vec(r, "r")
+        y = torch.empty_like(r) if y is None else y
+        check(lib().lgp_ilu_forward(self.handle, _ptr(r), _ptr(y), _stream()), "lgp_ilu_forward")
+        return y
+
+    def backward(self, y: torch.Tensor, z: torch.Tensor = None) -> torch.Tensor:
+        self._vec(y, "y")
+        z = torch.empty_like(y) if z is None else z
+        check(lib().lgp_ilu_backward(self.handle, _ptr(y), _ptr(z), _stream()), "lgp_ilu_backward")
+        return z
+
+    def describe(self):
+        """Pattern (offsets, n_lower) and views of the factor storage."""
+        dsc = lgpcg.FactorDesc()
+        check(lib().lgp_factor_describe(self.handle, ctypes.byref(dsc)), "lgp_factor_describe")
+        offs = [(dsc.offsets[3 * k], dsc.offsets[3 * k + 1], dsc.offsets[3 * k + 2]) for k in range(dsc.noff)]
+        n, nlo = dsc.n, dsc.n_lower
+        base = self.buf.data_ptr()
+        Lv = self.buf[dsc.L - base: dsc.L - base + n * nlo * 8].view(torch.float64).view(n, nlo)
+        Dv = self.buf[dsc.D - base: dsc.D - base + n * 8].view(torch.float64)
+        return dict(offsets=offs, n_lower=nlo, L=Lv, D=Dv, levels=dsc.levels, n=n)
+
+
+def pcg_solve(problem: Problem, factor: Factor, F: torch.Tensor, x: torch.Tensor = None, rtol: float = 1e-10,
+              max_iter: int = 2000, inner: str = "f64", inner_rtol: float = 1e-4, max_outer: int = 60,
+              check_every: int = 4, ws: torch.Tensor = None, raise_on_error: bool = True):
+    """Solve K x = F by PCG (Alg. 1) with the one-step ILU(0) preconditioner.
+    Returns (x, info dict). `x` is used as the initial guess (zeros if None)."""
+    L = lib()
+    _need(F, torch.float64, problem.n, "F")
+    if x is None:
+        x = torch.zeros_like(F)
+    _need(x, torch.float64, problem.n, "x")
+    nbytes = L.lgp_solve_workspace_bytes(problem.handle, DTYPES[inner])
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    o = lgpcg.SolveOpts(rtol, max_iter, DTYPES[inner], inner_rtol, max_outer, check_every)
+    info = lgpcg.SolveInfo()
+    st = L.lgp_pcg_solve(problem.handle, factor.handle, _ptr(F), _ptr(x), ctypes.byref(o), _ptr(ws),
+                         ws.numel(), _stream(), ctypes.byref(info))
+    out = dict(iters=info.iters, outer=info.outer, relres_true=info.relres_true,
+               relres_recursive=info.relres_recursive, status=lgpcg.STATUS.get(st, st))
+    if st != 0 and raise_on_error:
+        raise lgpcg.LgpError(st, "lgp_pcg_solve")
+    return x, out
