@@ -60,8 +60,10 @@ static int *offset_cube(const grid_t *g, int *R) {
     return cube;
 }
 
-/* Alg. 2 in place on H. Returns 0, or 1 + row of the first zero pivot. */
-int64_t ilu0_stencil(int d, int n1, int noff, const int *off, double *H) {
+/* Alg. 2 in place on H for rows 0..nrows-1 (nrows < 0: all rows). Rows only
+   depend on earlier rows, so a prefix is exactly the same computation as in
+   the full factorisation. Returns 0, or 1 + row of the first zero pivot. */
+int64_t ilu0_stencil(int d, int n1, int noff, const int *off, double *H, int64_t nrows) {
     grid_t g = {d, n1, noff, -1, off};
     for (int o = 0; o < noff; ++o)
         if (off[3 * o] == 0 && off[3 * o + 1] == 0 && off[3 * o + 2] == 0) g.diag = o;
@@ -95,6 +97,7 @@ int64_t ilu0_stencil(int d, int n1, int noff, const int *off, double *H) {
     free(cube);
     int64_t n = 1;
     for (int k = 0; k < d; ++k) n *= n1;
+    if (nrows >= 0 && nrows < n) n = nrows;
     for (int64_t i = 0; i < n; ++i) {
         int c[3];
         coords(&g, i, c);

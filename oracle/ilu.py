@@ -87,7 +87,7 @@ def _clib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         _lib.ilu0_stencil.restype = ctypes.c_int64
-        _lib.ilu0_stencil.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp]
+        _lib.ilu0_stencil.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, ctypes.c_int64]
         for f in (_lib.forward_stencil, _lib.backward_stencil):
             f.restype = None
             f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp]
@@ -118,9 +118,12 @@ class StencilILU:
         self.H = np.ascontiguousarray(H, dtype=np.float64)
         self.diag = self.offsets.index(tuple([0] * d))
 
-    def factor(self):
+    def factor(self, nrows: int = -1):
+        """Alg. 2 over all rows, or over the first `nrows` rows only (a prefix
+        is the same computation as in the full factorisation; used to time a
+        bounded sample)."""
         rc = _clib().ilu0_stencil(self.d, self.n1, len(self.offsets),
-                                  _p(self.off, ctypes.c_int), _p(self.H, ctypes.c_double))
+                                  _p(self.off, ctypes.c_int), _p(self.H, ctypes.c_double), nrows)
         if rc != 0:
             raise ZeroDivisionError("zero pivot in ILU(0) at row %d" % (rc - 1))
         return self

@@ -104,14 +104,28 @@ size_t plan_factor(Factor& F, void* buf, bool with32) {
 }
 
 // ------------------------------------------------------ device helpers ---
-__device__ inline unsigned ld_acquire(const unsigned* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline unsigned ld_relaxed(const unsigned* p) {
+// Values produced and consumed inside one kernel by different workgroups
+// (substitution results, factor rows, pivots, progress flags) travel through
+// device-coherent accesses: relaxed device-scope atomic loads and stores,
+// which the compiler emits as sc1 global accesses and which need no L2
+// write-back or invalidate. A producer waits for its own stores to complete
+// (s_waitcnt vmcnt(0)) before it publishes a flag, so a consumer that has
+// seen the flag and then loads coherently sees the data. Data written by an
+// earlier kernel (the factors, the right-hand side) is read with ordinary
+// cached loads.
+template <typename T>
+__device__ inline T ld_coh(const T* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void st_release(unsigned* p, unsigned v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+template <typename T>
+__device__ inline void st_coh(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void wait_own_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ inline void compiler_fence() { asm volatile("" ::: "memory"); }
+__device__ inline void publish(unsigned* flag, unsigned v) {
+    wait_own_stores();
+    st_coh(flag, v);
 }
 
 __device__ inline double wave_sum(double v) {
@@ -234,13 +248,14 @@ __global__ __launch_bounds__(64) void ilu_factor_kernel(
             if (!in) continue;   // uniform across the wave
             const int64_t rj = i + oj.w;
             if (lane == 0) {
-                while (ld_acquire(&done[rj]) == 0u) __builtin_amdgcn_s_sleep(1);
+                while (ld_coh(&done[rj]) == 0u) __builtin_amdgcn_s_sleep(1);
             }
             __syncthreads();
+            compiler_fence();
             double acc = 0.0;
             const double* Lj = L + rj * nlo;
             for (int p = pair_ptr[j] + lane; p < pair_ptr[j + 1]; p += 64)
-                acc += u[pair_k[p]] * Lj[pair_l[p]];
+                acc += u[pair_k[p]] * ld_coh(&Lj[pair_l[p]]);
             acc = wave_sum(acc);
             if (lane == 0) u[j] = u[j] - acc;
             __syncthreads();
@@ -253,20 +268,20 @@ __global__ __launch_bounds__(64) void ilu_factor_kernel(
             const bool in = (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1);
             double lk = 0.0;
             if (in) {
-                lk = u[k] / Dg[i + o.w];
+                lk = u[k] / ld_coh(&Dg[i + o.w]);
                 acc += u[k] * lk;
             }
-            L[i * nlo + k] = lk;
+            st_coh(&L[i * nlo + k], lk);
         }
         acc = wave_sum(acc);
         if (lane == 0) {
             const double piv = u[nlo] - acc;
             if (!(piv > 0.0) || !isfinite(piv)) atomicOr(flag, 1);
-            Dg[i] = piv;
+            st_coh(&Dg[i], piv);
             invD[i] = 1.0 / piv;
         }
         __syncthreads();
-        if (lane == 0) st_release(&done[i], 1u);
+        if (lane == 0) publish(&done[i], 1u);
         __syncthreads();
     }
 }
@@ -334,16 +349,17 @@ __global__ __launch_bounds__(NT) void sweep_kernel(int d, int n1, int64_t n, int
             if (tid == 0) {
                 if (dep0 >= 0 && s_have[0] < need) {
                     unsigned v;
-                    while ((v = ld_acquire(&prog[dep0])) < need) __builtin_amdgcn_s_sleep(1);
+                    while ((v = ld_coh(&prog[dep0])) < need) __builtin_amdgcn_s_sleep(1);
                     s_have[0] = v;
                 }
                 if (dep1 >= 0 && s_have[1] < need) {
                     unsigned v;
-                    while ((v = ld_acquire(&prog[dep1])) < need) __builtin_amdgcn_s_sleep(1);
+                    while ((v = ld_coh(&prog[dep1])) < need) __builtin_amdgcn_s_sleep(1);
                     s_have[1] = v;
                 }
             }
             __syncthreads();
+            compiler_fence();
             const int64_t rp = (int64_t)line * n1 + ix;         // stream row
             const int64_t rm = REV ? (n - 1 - rp) : rp;          // memory row
             T acc = T(0);
@@ -352,7 +368,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel(int d, int n1, int64_t n, int
                 const int cx = ix + o.x, cy = ly + o.y, cz = lz + o.z;
                 if (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1) {
                     const int64_t nb = REV ? (rm - o.w) : (rm + o.w);
-                    acc += A[rp * nlo + k] * out[nb];
+                    acc += A[rp * nlo + k] * ld_coh(&out[nb]);
                 }
             }
             acc = wave_sum(acc);
@@ -365,10 +381,11 @@ __global__ __launch_bounds__(NT) void sweep_kernel(int d, int n1, int64_t n, int
             if (tid == 0) {
                 T v = in[rm];
                 if (SCALE) v *= scale[rm];
-                out[rm] = v - acc;
+                st_coh(&out[rm], v - acc);
+                wait_own_stores();
             }
             __syncthreads();
-            if (tid == 0 && (ix == n1 - 1 || ((ix + 1) & 7) == 0)) st_release(&prog[line], (unsigned)(ix + 1));
+            if (tid == 0 && (ix == n1 - 1 || ((ix + 1) & 7) == 0)) publish(&prog[line], (unsigned)(ix + 1));
         }
         __syncthreads();
     }
