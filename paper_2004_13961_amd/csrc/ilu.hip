@@ -137,6 +137,38 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
+// Wave-wide sum with DPP lane moves inside each row of 16 lanes (pair swap,
+// quad swap, half-row mirror, row mirror), then the four row sums combined
+// through readlane; every lane returns the same value.
+template <int CTRL>
+__device__ inline int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline double dpp_v(double v) {
+    const int lo = dpp_i<CTRL>(__double2loint(v));
+    const int hi = dpp_i<CTRL>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ inline float dpp_v(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+__device__ inline double lane_val(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float lane_val(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+template <typename T>
+__device__ inline T wave_sum_dpp(T v) {
+    v += dpp_v<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_v<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_v<0x141>(v);   // row_half_mirror
+    v += dpp_v<0x140>(v);   // row_mirror
+    return (lane_val(v, 0) + lane_val(v, 16)) + (lane_val(v, 32) + lane_val(v, 48));
+}
+
 struct RowGeo {
     int n1, d;
     int64_t n;
@@ -391,6 +423,219 @@ __global__ __launch_bounds__(NT) void sweep_kernel(int d, int n1, int64_t n, int
     }
 }
 
+// Sentinel marking a substitution result that is not written yet: a NaN
+// payload that arithmetic never produces (computed NaNs are stored as the
+// canonical quiet NaN instead), so polling the value itself tells a
+// consumer whether it is ready.
+template <typename T> struct Sentinel;
+template <> struct Sentinel<double> {
+    static __device__ __host__ inline double value() { return __longlong_as_double(0x7FF40000DEADBEEFll); }
+    static __device__ inline bool is(double v) { return __double_as_longlong(v) == 0x7FF40000DEADBEEFll; }
+    static __device__ inline double clean(double v) { return isnan(v) ? __longlong_as_double(0x7FF8000000000000ll) : v; }
+};
+template <> struct Sentinel<float> {
+    static __device__ __host__ inline float value() { return __int_as_float(0x7FA0BEEF); }
+    static __device__ inline bool is(float v) { return __float_as_int(v) == 0x7FA0BEEF; }
+    static __device__ inline float clean(float v) { return isnan(v) ? __int_as_float(0x7FC00000) : v; }
+};
+
+template <typename T>
+__global__ void fill_sentinel_kernel(int64_t n, T* __restrict__ out, const int* __restrict__ stop) {
+    if (stop && *stop) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = Sentinel<T>::value();
+}
+
+// 2D substitution, banded. A workgroup owns B consecutive grid lines (one
+// wave per line) and walks them as a pipeline; all operands of the row dot
+// products come from LDS, which holds full lines: the Hy lines preceding
+// the band (written by earlier workgroups) and the band's own B lines.
+// Every dependency is carried by the value itself: the LDS line buffers and
+// the output in device memory are pre-filled with a sentinel, so a value is
+// ready exactly when it is no longer the sentinel. There are no progress
+// counters and no waits for store completion; a consumer that reads a
+// sentinel simply reads again (rare path).
+//   * Own line and earlier lines of the band: written to LDS by their waves.
+//   * Earlier bands: wave 0 stages one new column of the Hy preceding lines
+//     per row (lanes 0..Hy-1) from device memory into LDS, with the device
+//     loads issued D rows ahead.
+//   * The static factor rows and the right-hand side are loaded D rows
+//     ahead into registers; LDS reads are unconditional (entries outside the
+//     grid read a zero slot) so a row waits on LDS once.
+//   * Results go to device memory once per group of D rows, except for the
+//     band's last line, which the next band reads with no slack (every row).
+__device__ inline void wait_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// sleep 64*nap cycles, doubling nap up to 64 (about 1.7 us)
+__device__ inline void backoff(int& nap) {
+    for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(1);
+    if (nap < 64) nap <<= 1;
+}
+
+template <typename T, int MK, int D, int B, bool REV, bool SCALE>
+__global__ __launch_bounds__(64 * B) void sweep2d_band_kernel(int n1, int64_t n, int nlo,
+                                                              const int4* __restrict__ offs,
+                                                              const T* __restrict__ A, const T* __restrict__ scale,
+                                                              const T* __restrict__ in, T* __restrict__ out,
+                                                              unsigned* ticket, const int* __restrict__ stop,
+                                                              int Hx, int Hy) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T* lb = (T*)smem_raw;                     // [Hy + B][n1] line buffers, then one zero slot
+    __shared__ int s_band;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (stop && *stop) return;
+    const int nbands = (n1 + B - 1) / B;
+    const int nl = Hy + B;
+    const int zslot = nl * n1;
+
+    int odx[MK], ody[MK], kcl[MK];
+    bool oval[MK];
+#pragma unroll
+    for (int m = 0; m < MK; ++m) {
+        const int k = lane + 64 * m;
+        oval[m] = k < nlo;
+        kcl[m] = oval[m] ? k : nlo - 1;
+        const int4 o = offs[kcl[m]];
+        odx[m] = o.x;
+        ody[m] = o.y;
+    }
+
+    for (;;) {
+        if (tid == 0) {
+            const unsigned tk = atomicAdd(ticket, 1u);
+            s_band = (tk < (unsigned)nbands) ? (int)tk : -1;
+        }
+        for (int e = tid; e < zslot; e += 64 * B) lb[e] = Sentinel<T>::value();
+        if (tid == 0) lb[zslot] = T(0);
+        __syncthreads();
+        const int band = __builtin_amdgcn_readfirstlane(s_band);
+        if (band < 0) break;
+        const int L = band * B + w;
+        const int first = band * B;
+        const int lbase = first - Hy;   // line held in lb row 0
+        if (L < n1) {
+            const int64_t rowbase = (int64_t)L * n1;
+            const int64_t mbase = REV ? (n - 1 - rowbase) : rowbase;
+            const T* Aline = A + rowbase * nlo;
+            int loff[MK];
+            bool lok[MK];
+#pragma unroll
+            for (int m = 0; m < MK; ++m) {
+                const int ly = L + ody[m];
+                lok[m] = oval[m] && ly >= 0 && ly < n1;
+                loff[m] = lok[m] ? (ly - lbase) * n1 + odx[m] : 0;
+            }
+            T a_s[D][MK];
+            T r_s[D];
+            auto issue = [&](int s, int ixp) {
+                ixp = min(ixp, n1 - 1);
+                const T* Ar = Aline + (int64_t)ixp * nlo;
+                const int64_t rm = REV ? (mbase - ixp) : (mbase + ixp);
+#pragma unroll
+                for (int m = 0; m < MK; ++m) a_s[s][m] = Ar[kcl[m]];
+                // vector loads (a relaxed atomic is never turned into a scalar
+                // load; scalar loads share lgkmcnt with LDS)
+                T rv = __hip_atomic_load(&in[rm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (SCALE) rv *= __hip_atomic_load(&scale[rm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                r_s[s] = rv;
+            };
+            const bool stager = (w == 0) && (first > 0) && (lane < Hy) && (lbase + lane >= 0);
+            const int sline = lbase + lane;
+            auto saddr = [&](int x) {
+                x = min(x, n1 - 1);
+                const int64_t rp = (int64_t)(stager ? sline : 0) * n1 + x;
+                return REV ? (n - 1 - rp) : rp;
+            };
+            T st_v[D];
+            // stage column x (value v loaded earlier; re-read while not ready)
+            auto stage_now = [&](int x, T v) {
+                const bool act = stager && x < n1;
+                if (__builtin_expect(__any(act && Sentinel<T>::is(v)), 0)) {
+                    int nap = 1;
+                    while (act && Sentinel<T>::is(v)) {
+                        backoff(nap);
+                        v = ld_coh(&out[saddr(x)]);
+                    }
+                }
+                if (act) lb[lane * n1 + x] = v;
+            };
+            if (w == 0 && first > 0) {
+                for (int x = 0; x < Hx && x < n1; ++x) stage_now(x, stager ? ld_coh(&out[saddr(x)]) : T(0));
+#pragma unroll
+                for (int s = 0; s < D; ++s) st_v[s] = stager ? ld_coh(&out[saddr(Hx + s)]) : T(0);
+            }
+            auto row = [&](int s, int ix) -> T {
+                if (w == 0 && first > 0) {
+                    const int x = ix + Hx;
+                    stage_now(x, st_v[s]);
+                    st_v[s] = stager ? ld_coh(&out[saddr(x + D)]) : T(0);
+                }
+                int idx[MK];
+#pragma unroll
+                for (int m = 0; m < MK; ++m) {
+                    const bool ok = lok[m] && (unsigned)(ix + odx[m]) < (unsigned)n1;
+                    idx[m] = ok ? loff[m] + ix : zslot;
+                }
+                T yv[MK];
+#pragma unroll
+                for (int m = 0; m < MK; ++m) yv[m] = lb[idx[m]];
+                bool miss = false;
+#pragma unroll
+                for (int m = 0; m < MK; ++m) miss |= Sentinel<T>::is(yv[m]);
+                if (__builtin_expect(__any(miss), 0)) {
+#pragma unroll
+                    for (int m = 0; m < MK; ++m) {
+                        while (Sentinel<T>::is(yv[m])) {
+                            __builtin_amdgcn_s_sleep(1);
+                            yv[m] = __hip_atomic_load(&lb[idx[m]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                    }
+                }
+                T acc = T(0);
+#pragma unroll
+                for (int m = 0; m < MK; ++m) acc += (idx[m] == zslot ? T(0) : a_s[s][m]) * yv[m];
+                return wave_sum_dpp(acc);
+            };
+            T* lbw = lb + (Hy + w) * n1;
+            const bool last_line = (w == B - 1) || (L == n1 - 1);
+            auto mrow = [&](int ixp) { return REV ? (mbase - ixp) : (mbase + ixp); };
+#pragma unroll
+            for (int s = 0; s < D; ++s) issue(s, s);
+            int ix0 = 0;
+            for (; ix0 + D <= n1; ix0 += D) {
+#pragma unroll
+                for (int s = 0; s < D; ++s) {
+                    const int ix = ix0 + s;
+                    const T acc = row(s, ix);
+                    const T y = Sentinel<T>::clean(r_s[s] - acc);
+                    issue(s, ix + D);
+                    if (lane == 0) {
+                        lbw[ix] = y;
+                        if (last_line) st_coh(&out[mrow(ix)], y);
+                    }
+                }
+                if (!last_line) {
+                    wait_lds();
+                    if (lane < D) st_coh(&out[mrow(ix0 + lane)], lbw[ix0 + lane]);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < D; ++s) {
+                const int ix = ix0 + s;
+                if (ix < n1) {
+                    const T acc = row(s, ix);
+                    const T y = Sentinel<T>::clean(r_s[s] - acc);
+                    if (lane == 0) lbw[ix] = y;
+                }
+            }
+            wait_lds();
+            if (lane < n1 - ix0) st_coh(&out[mrow(ix0 + lane)], lbw[ix0 + lane]);
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void reset_kernel(unsigned* p, int count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
@@ -535,7 +780,29 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, tick, 1);
     LGP_CHECK_LAUNCH();
     const int64_t n = F.n;
-    if (F.d == 2) {
+    constexpr int BB = 8, DD = 8;
+    const size_t band_shmem = ((size_t)(BB + F.Hy) * F.n1 + 1) * sizeof(T);
+    if (F.d == 2 && F.nlo <= 8 * 64 && band_shmem <= 150 * 1024) {
+        const int nbands = (F.n1 + BB - 1) / BB;
+        hipLaunchKernelGGL(fill_sentinel_kernel<T>, dim3(std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, s,
+                           n, out, stop);
+        auto pick = [&](auto kf) {
+            hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)band_shmem);
+            const int grid = persistent_grid((const void*)kf, 64 * BB, band_shmem, nbands);
+            hipLaunchKernelGGL(kf, dim3(grid), dim3(64 * BB), band_shmem, s, F.n1, n, F.nlo, (const int4*)F.d_offs,
+                               A, scale, in, out, tick, stop, F.Hx, F.Hy);
+        };
+        if (F.nlo <= 128) {
+            if (backward) pick(sweep2d_band_kernel<T, 2, DD, BB, true, true>);
+            else pick(sweep2d_band_kernel<T, 2, DD, BB, false, false>);
+        } else if (F.nlo <= 256) {
+            if (backward) pick(sweep2d_band_kernel<T, 4, DD, BB, true, true>);
+            else pick(sweep2d_band_kernel<T, 4, DD, BB, false, false>);
+        } else {
+            if (backward) pick(sweep2d_band_kernel<T, 8, DD, BB, true, true>);
+            else pick(sweep2d_band_kernel<T, 8, DD, BB, false, false>);
+        }
+    } else if (F.d == 2) {
         auto kf = backward ? sweep_kernel<T, 64, true, true> : sweep_kernel<T, 64, false, false>;
         const int grid = persistent_grid((const void*)kf, 64, 0, F.nlines);
         hipLaunchKernelGGL(kf, dim3(grid), dim3(64), 0, s, F.d, F.n1, n, F.nlo, (const int4*)F.d_offs,
