@@ -9,6 +9,8 @@
 // applied direction by direction as matrix-core contractions (gemm.hip).
 // W is the tensor Gauss weight, so sum_nodes W g v is exactly (I_N g, v).
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "lgp_internal.h"
 
@@ -144,42 +146,68 @@ static inline int grid_for(int64_t n, int bs = 256, int cap = 4096) {
 }
 
 // ------------------------------------------------------------- setup -----
-lgp_status build_tables(Problem& P, hipStream_t s) {
-    const int n1 = P.n1, q = P.q, N = P.N;
-    gauss_legendre_host(N, P.x, P.w);
-    const size_t tab = (size_t)n1 * 2 * q;
-    std::vector<double> PDT(tab), PhiD(tab), DP(tab);
-    std::vector<float> PDT32(tab), PhiD32(tab), DP32(tab);
-    std::vector<long double> L(N + 2);
-    for (int m = 0; m < q; ++m) {
-        const long double z = P.x[m];
-        L[0] = 1.0L;
-        L[1] = z;
-        for (int k = 1; k <= N; ++k) L[k + 1] = ((2 * k + 1) * z * L[k] - k * L[k - 1]) / (k + 1);
-        for (int k = 0; k < n1; ++k) {
-            const double phi = (double)(L[k] - L[k + 2]);
-            const double dphi = (double)(-(2 * k + 3) * L[k + 1]);
-            PDT[(size_t)k * 2 * q + m] = phi;
-            PDT[(size_t)k * 2 * q + q + m] = dphi;
-            PhiD[(size_t)m * n1 + k] = phi;
-            PhiD[(size_t)(q + m) * n1 + k] = dphi;
-            DP[(size_t)m * n1 + k] = dphi;
-            DP[(size_t)(q + m) * n1 + k] = phi;
+// Nodes and weights depend only on N: computed once per N on the host
+// (extended-precision Newton) and kept for the life of the process.
+static std::mutex g_node_mu;
+static std::map<int, std::pair<std::vector<double>, std::vector<double>>> g_nodes;
+
+static void cached_nodes(int N, std::vector<double>& x, std::vector<double>& w) {
+    {
+        std::lock_guard<std::mutex> lk(g_node_mu);
+        auto it = g_nodes.find(N);
+        if (it != g_nodes.end()) {
+            x = it->second.first;
+            w = it->second.second;
+            return;
         }
     }
-    for (size_t i = 0; i < tab; ++i) {
-        PDT32[i] = (float)PDT[i];
-        PhiD32[i] = (float)PhiD[i];
-        DP32[i] = (float)DP[i];
+    gauss_legendre_host(N, x, w);
+    std::lock_guard<std::mutex> lk(g_node_mu);
+    g_nodes[N] = {x, w};
+}
+
+// One thread per node: the three-term recurrence in FP64 gives L_0..L_{N+1}
+// at x_m, from which phi_k = L_k - L_{k+2} and phi_k' = -(2k+3) L_{k+1}
+// fill the four table layouts (FP64 and FP32 copies).
+__global__ void tables_kernel(int N, const double* __restrict__ xn, double* __restrict__ PDT,
+                              double* __restrict__ PhiD, double* __restrict__ DP, float* __restrict__ PDT32,
+                              float* __restrict__ PhiD32, float* __restrict__ DP32) {
+    const int q = N + 1, n1 = N - 1;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= q) return;
+    const double z = xn[m];
+    double l0 = 1.0, l1 = z, l2 = ((3.0 * z) * l1 - 1.0 * l0) / 2.0;   // L_0, L_1, L_2
+    for (int k = 0; k < n1; ++k) {
+        // here l0 = L_k, l1 = L_{k+1}, l2 = L_{k+2}
+        const double phi = l0 - l2;
+        const double dphi = -(2.0 * k + 3.0) * l1;
+        PDT[(size_t)k * 2 * q + m] = phi;
+        PDT[(size_t)k * 2 * q + q + m] = dphi;
+        PhiD[(size_t)m * n1 + k] = phi;
+        PhiD[(size_t)(q + m) * n1 + k] = dphi;
+        DP[(size_t)m * n1 + k] = dphi;
+        DP[(size_t)(q + m) * n1 + k] = phi;
+        PDT32[(size_t)k * 2 * q + m] = (float)phi;
+        PDT32[(size_t)k * 2 * q + q + m] = (float)dphi;
+        PhiD32[(size_t)m * n1 + k] = (float)phi;
+        PhiD32[(size_t)(q + m) * n1 + k] = (float)dphi;
+        DP32[(size_t)m * n1 + k] = (float)dphi;
+        DP32[(size_t)(q + m) * n1 + k] = (float)phi;
+        const int j = k + 2;   // L_{j+1} = ((2j+1) z L_j - j L_{j-1}) / (j+1)
+        const double l3 = ((2.0 * j + 1.0) * z * l2 - j * l1) / (j + 1.0);
+        l0 = l1;
+        l1 = l2;
+        l2 = l3;
     }
-    LGP_HIP(hipMemcpyAsync(P.PDT, PDT.data(), tab * 8, hipMemcpyHostToDevice, s));
-    LGP_HIP(hipMemcpyAsync(P.PhiD, PhiD.data(), tab * 8, hipMemcpyHostToDevice, s));
-    LGP_HIP(hipMemcpyAsync(P.DP, DP.data(), tab * 8, hipMemcpyHostToDevice, s));
-    LGP_HIP(hipMemcpyAsync(P.PDT32, PDT32.data(), tab * 4, hipMemcpyHostToDevice, s));
-    LGP_HIP(hipMemcpyAsync(P.PhiD32, PhiD32.data(), tab * 4, hipMemcpyHostToDevice, s));
-    LGP_HIP(hipMemcpyAsync(P.DP32, DP32.data(), tab * 4, hipMemcpyHostToDevice, s));
-    // the host vectors must stay alive until the copies finish
-    LGP_HIP(hipStreamSynchronize(s));
+}
+
+lgp_status build_tables(Problem& P, hipStream_t s) {
+    cached_nodes(P.N, P.x, P.w);
+    // nodes in s3 (setup_nodes puts the weights in s2 afterwards)
+    LGP_HIP(hipMemcpyAsync(P.s3, P.x.data(), P.q * 8, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(tables_kernel, dim3((P.q + 127) / 128), dim3(128), 0, s, P.N, (const double*)P.s3, P.PDT,
+                       P.PhiD, P.DP, P.PDT32, P.PhiD32, P.DP32);
+    LGP_CHECK_LAUNCH();
     return LGP_OK;
 }
 
