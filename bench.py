@@ -184,11 +184,11 @@ def main():
     for _ in range(nsw):
         M.forward(u, y)
     ev[3].record()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     M_t = Factor(P, T)
     torch.cuda.synchronize()
     t_factor = time.perf_counter() - t0
-    torch.cuda.synchronize()
     mv_ms = ev[0].elapsed_time(ev[1]) / nmv
     sw_ms = ev[2].elapsed_time(ev[3]) / nsw
     mv_tflops = matvec_flops(d, N) / (mv_ms * 1e-3) / 1e12

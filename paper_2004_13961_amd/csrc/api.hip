@@ -279,6 +279,7 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
         }
     }
     if (st != LGP_OK) {
+        hipStreamSynchronize(s);   // FT must outlive its queued copy
         delete hF;
         return st;
     }
@@ -302,6 +303,7 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
     }
     if (hipMemcpyAsync(F.coefA, ca.data(), tp * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(F.coefB, cb.data(), tp * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
+        hipStreamSynchronize(s);   // ca, cb must outlive their queued copies
         delete hF;
         return LGP_E_HIP;
     }
@@ -356,6 +358,7 @@ lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out) {
     out->L = F.L;
     out->D = F.Dg;
     out->levels = F.levels;
+    out->ld = F.ldl;
     return LGP_OK;
 }
 

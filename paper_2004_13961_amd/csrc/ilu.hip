@@ -35,22 +35,22 @@ namespace lgp {
 //   2/(2g+1) * C_{g-m} C_{g-n} C_{g-t} / C_g,  C_r = (2r-1)!!/(r! 2^r).
 // The large-index ratio C_{g-t}/C_g = prod_{r=g-t+1}^{g} 2r/(2r-1) has only
 // t factors; C_{g-m}, C_{g-n} have small indices when t is small.
-static double Cr(int r) {
+__host__ __device__ static inline double Cr(int r) {
     double c = 1.0;
     for (int i = 1; i <= r; ++i) c *= (2.0 * i - 1.0) / (2.0 * i);
     return c;
 }
 
-double triple_legendre(int t, int m, int n) {
+__host__ __device__ double triple_legendre(int t, int m, int n) {
     if (t < 0 || m < 0 || n < 0) return 0.0;
     if ((t + m + n) & 1) return 0.0;
-    if (t > m + n || t < std::abs(m - n)) return 0.0;
+    if (t > m + n || t < abs(m - n)) return 0.0;
     const int g = (t + m + n) / 2;
     // order so that the two small indices use direct products
     int small1 = g - m, small2 = g - n, big = g - t;
     // if t is the largest of the three, g-t is the smallest: swap roles so
     // that the ratio is taken against the smallest of (t, m, n)
-    int lo = std::min(t, std::min(m, n));
+    int lo = min(t, min(m, n));
     if (lo != t) {
         if (lo == m) { small1 = g - t; big = g - m; }
         else         { small2 = g - t; big = g - n; }
@@ -61,9 +61,9 @@ double triple_legendre(int t, int m, int n) {
 }
 
 // S^(t)(i, m) = (2i+3)(2m+3) int L_t L_{i+1} L_{m+1}
-static double S1(int t, int i, int m) { return (2.0 * i + 3) * (2.0 * m + 3) * triple_legendre(t, i + 1, m + 1); }
+__host__ __device__ static inline double S1(int t, int i, int m) { return (2.0 * i + 3) * (2.0 * m + 3) * triple_legendre(t, i + 1, m + 1); }
 // M^(t)(i, m) = int L_t (L_i - L_{i+2}) (L_m - L_{m+2})
-static double M1(int t, int i, int m) {
+__host__ __device__ static inline double M1(int t, int i, int m) {
     return triple_legendre(t, i, m) - triple_legendre(t, i, m + 2) - triple_legendre(t, i + 2, m) +
            triple_legendre(t, i + 2, m + 2);
 }
@@ -75,14 +75,16 @@ size_t plan_factor(Factor& F, void* buf, bool with32) {
     const int T = F.T, h = F.h, d = F.d, n1 = F.n1;
     int64_t tp = 1;
     for (int k = 0; k < d; ++k) tp *= (T + 1);
-    F.L = c.take<double>((size_t)n * nlo);
-    F.Ut = c.take<double>((size_t)n * nlo);
+    F.ldl = ((nlo + 1) + 15) & ~15;
+    const size_t ldl = (size_t)F.ldl;
+    F.L = c.take<double>((size_t)(n + 1) * ldl);
+    F.Ut = c.take<double>((size_t)n * ldl);
     F.Dg = c.take<double>(n);
     F.invD = c.take<double>(n);
     F.has32 = with32;
     if (with32) {
-        F.L32 = c.take<float>((size_t)n * nlo);
-        F.Ut32 = c.take<float>((size_t)n * nlo);
+        F.L32 = c.take<float>((size_t)n * ldl);
+        F.Ut32 = c.take<float>((size_t)n * ldl);
         F.invD32 = c.take<float>(n);
     } else {
         F.L32 = F.Ut32 = F.invD32 = nullptr;
@@ -98,6 +100,15 @@ size_t plan_factor(Factor& F, void* buf, bool with32) {
     F.pair_ptr = c.take<int>(nlo + 2);
     F.pair_j = c.take<int>(F.npairs > 0 ? F.npairs : 1);
     F.pair_l = c.take<int>(F.npairs > 0 ? F.npairs : 1);
+    F.steps = c.take<int>((size_t)4 * (nlo + 1));
+    F.sdxyz = c.take<int>(nlo + 1);
+    F.pairw = c.take<unsigned>(F.npairs > 0 ? F.npairs : 1);
+    {
+        const int64_t A1 = F.Hx + 1, B1 = (int64_t)(F.Hx + 1) * (F.Hy + 1);
+        F.maxlev = (int)((n1 - 1) * (1 + A1 + (d == 3 ? B1 : 0)) + 1);
+    }
+    F.lev = c.take<int>((size_t)2 * F.maxlev + 2);
+    F.runs = c.take<int>((size_t)4 * (nlo + 1));
     F.y_tmp = c.take<double>(n);
     F.bytes = c.off + 256;
     return F.bytes;
@@ -231,7 +242,7 @@ __global__ void fold_kernel(int d, int n1, int T, int h, const double* __restric
 // ---------------------------------------------------- factorisation ------
 // One wave per row. LDS: u[0..nlo] (u[nlo] = diagonal), offsets table.
 __global__ __launch_bounds__(64) void ilu_factor_kernel(
-    int d, int n1, int64_t n, int nlo, int T, int h, const int4* __restrict__ offs,
+    int d, int n1, int64_t n, int nlo, int ldl, int T, int h, const int4* __restrict__ offs,
     const int* __restrict__ row_order, const double* __restrict__ band, const double* __restrict__ fold,
     const int* __restrict__ pair_ptr, const int* __restrict__ pair_k, const int* __restrict__ pair_l,
     double* __restrict__ L, double* __restrict__ Dg, double* __restrict__ invD, unsigned* done,
@@ -285,7 +296,7 @@ __global__ __launch_bounds__(64) void ilu_factor_kernel(
             __syncthreads();
             compiler_fence();
             double acc = 0.0;
-            const double* Lj = L + rj * nlo;
+            const double* Lj = L + rj * ldl;
             for (int p = pair_ptr[j] + lane; p < pair_ptr[j + 1]; p += 64)
                 acc += u[pair_k[p]] * ld_coh(&Lj[pair_l[p]]);
             acc = wave_sum(acc);
@@ -303,7 +314,7 @@ __global__ __launch_bounds__(64) void ilu_factor_kernel(
                 lk = u[k] / ld_coh(&Dg[i + o.w]);
                 acc += u[k] * lk;
             }
-            st_coh(&L[i * nlo + k], lk);
+            st_coh(&L[i * ldl + k], lk);
         }
         acc = wave_sum(acc);
         if (lane == 0) {
@@ -311,6 +322,7 @@ __global__ __launch_bounds__(64) void ilu_factor_kernel(
             if (!(piv > 0.0) || !isfinite(piv)) atomicOr(flag, 1);
             st_coh(&Dg[i], piv);
             invD[i] = 1.0 / piv;
+            L[i * ldl + nlo] = 1.0 / piv;
         }
         __syncthreads();
         if (lane == 0) publish(&done[i], 1u);
@@ -318,9 +330,79 @@ __global__ __launch_bounds__(64) void ilu_factor_kernel(
     }
 }
 
+// 1D band tables: band[t][i][delta+h] = S^(t)(i, i+delta), band[T+1+t][i][delta+h]
+// = M^(t)(i, i+delta) (Lemma LegProduct), zero outside 0 <= i+delta < n1.
+__global__ void band_kernel(int T, int n1, int h, double* __restrict__ band) {
+    const int W = 2 * h + 1, T1 = T + 1;
+    const int64_t total = (int64_t)T1 * n1 * W;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int dl = (int)(e % W) - h;
+        const int i = (int)((e / W) % n1);
+        const int t = (int)(e / ((int64_t)W * n1));
+        const int m = i + dl;
+        const bool in = m >= 0 && m < n1;
+        band[e] = in ? S1(t, i, m) : 0.0;
+        band[e + total] = in ? M1(t, i, m) : 0.0;
+    }
+}
+
+// Rows in nondecreasing hyperplane level l = ix + A1 iy + B1 iz: row i goes
+// to start[l] + (its rank among the rows of level l, taken by an atomic
+// counter; rows of one level are independent, so their order is free).
+__global__ void level_order_kernel(int d, int n1, int64_t n, int A1, int B1, const int* __restrict__ start,
+                                   int* fill, int* __restrict__ order) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int ix = (int)(i % n1), iy = (int)((i / n1) % n1);
+        const int iz = (d == 3) ? (int)(i / ((int64_t)n1 * n1)) : 0;
+        const int l = ix + A1 * iy + B1 * iz;
+        order[start[l] + atomicAdd(&fill[l], 1)] = (int)i;
+    }
+}
+
 // Backward-sweep operator in reversed row order: Ut[i'][k] = L(i - delta_k, i)
-// with i = n-1-i'.
-__global__ void build_ut_kernel(int d, int n1, int64_t n, int nlo, const int4* __restrict__ offs,
+// with i = n-1-i'. Tiled: a workgroup takes R consecutive output rows and
+// one run of offsets with equal (dy, dz) (consecutive k, dx ascending); the
+// source entries then lie in R + span consecutive rows of L and the run's
+// columns, staged through LDS so reads and writes are row segments.
+__global__ __launch_bounds__(256) void build_ut_tiled_kernel(int d, int n1, int64_t n, int ldl,
+                                                             const int4* __restrict__ offs,
+                                                             const int4* __restrict__ runs, int R,
+                                                             const double* __restrict__ L,
+                                                             double* __restrict__ Ut) {
+    extern __shared__ double tile[];
+    const int4 run = runs[blockIdx.y];   // {kb, ke, dx of kb, dx of ke-1}
+    const int kb = run.x, K = run.y - run.x, dxlo = run.z, dxhi = run.w;
+    const int span = dxhi - dxlo;
+    const int4 o0 = offs[kb];
+    const int64_t base = (int64_t)n1 * o0.y + (int64_t)n1 * n1 * o0.z;   // linear offset without dx
+    const int64_t p0 = (int64_t)blockIdx.x * R;
+    const int64_t rmin = n - 1 - (p0 + R - 1) - base - dxhi;
+    const int rows = R + span;
+    for (int e = threadIdx.x; e < rows * K; e += blockDim.x) {
+        const int rr = e / K, c = e - rr * K;
+        const int64_t r = rmin + rr;
+        tile[e] = (r >= 0 && r < n) ? L[r * ldl + kb + c] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * K; e += blockDim.x) {
+        const int pr = e / K, c = e - pr * K;
+        const int64_t ip = p0 + pr;
+        if (ip >= n) continue;
+        const int64_t i = n - 1 - ip;
+        const int4 o = offs[kb + c];
+        const int ix = (int)(i % n1), iy = (int)((i / n1) % n1);
+        const int iz = (d == 3) ? (int)(i / ((int64_t)n1 * n1)) : 0;
+        const int cx = ix - o.x, cy = iy - o.y, cz = iz - o.z;
+        const bool in = cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1;
+        const int64_t r = i - o.x - base;
+        Ut[ip * ldl + kb + c] = in ? tile[(r - rmin) * K + c] : 0.0;
+    }
+}
+
+// Backward-sweep operator in reversed row order: Ut[i'][k] = L(i - delta_k, i)
+// with i = n-1-i' (untiled form, for patterns whose runs do not fit LDS).
+__global__ void build_ut_kernel(int d, int n1, int64_t n, int nlo, int ldl, const int4* __restrict__ offs,
                                 const double* __restrict__ L, double* __restrict__ Ut) {
     const int64_t total = n * nlo;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -333,8 +415,8 @@ __global__ void build_ut_kernel(int d, int n1, int64_t n, int nlo, const int4* _
         const int4 o = offs[k];
         const int cx = ix - o.x, cy = iy - o.y, cz = iz - o.z;
         double v = 0.0;
-        if (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1) v = L[(i - o.w) * nlo + k];
-        Ut[e] = v;
+        if (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1) v = L[(i - o.w) * ldl + k];
+        Ut[ip * ldl + k] = v;
     }
 }
 
@@ -349,7 +431,7 @@ __global__ void to_f32_kernel(int64_t count, const double* __restrict__ a, float
 // stream position: r' = r forward, r' = n-1-r backward). Rows of a line run
 // in increasing stream order. NT threads per line.
 template <typename T, int NT, bool REV, bool SCALE>
-__global__ __launch_bounds__(NT) void sweep_kernel(int d, int n1, int64_t n, int nlo,
+__global__ __launch_bounds__(NT) void sweep_kernel(int d, int n1, int64_t n, int nlo, int ldl,
                                                    const int4* __restrict__ offs,
                                                    const int* __restrict__ line_order, int nlines,
                                                    int Hx, int Hy, const T* __restrict__ A,
@@ -400,7 +482,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel(int d, int n1, int64_t n, int
                 const int cx = ix + o.x, cy = ly + o.y, cz = lz + o.z;
                 if (cx >= 0 && cx < n1 && cy >= 0 && cy < n1 && cz >= 0 && cz < n1) {
                     const int64_t nb = REV ? (rm - o.w) : (rm + o.w);
-                    acc += A[rp * nlo + k] * ld_coh(&out[nb]);
+                    acc += A[rp * ldl + k] * ld_coh(&out[nb]);
                 }
             }
             acc = wave_sum(acc);
@@ -472,7 +554,7 @@ __device__ inline void backoff(int& nap) {
 }
 
 template <typename T, int MK, int D, int B, bool REV, bool SCALE>
-__global__ __launch_bounds__(64 * B) void sweep2d_band_kernel(int n1, int64_t n, int nlo,
+__global__ __launch_bounds__(64 * B) void sweep2d_band_kernel(int n1, int64_t n, int nlo, int ldl,
                                                               const int4* __restrict__ offs,
                                                               const T* __restrict__ A, const T* __restrict__ scale,
                                                               const T* __restrict__ in, T* __restrict__ out,
@@ -517,7 +599,7 @@ __global__ __launch_bounds__(64 * B) void sweep2d_band_kernel(int n1, int64_t n,
         if (L < n1) {
             const int64_t rowbase = (int64_t)L * n1;
             const int64_t mbase = REV ? (n - 1 - rowbase) : rowbase;
-            const T* Aline = A + rowbase * nlo;
+            const T* Aline = A + rowbase * ldl;
             int loff[MK];
             bool lok[MK];
 #pragma unroll
@@ -530,7 +612,7 @@ __global__ __launch_bounds__(64 * B) void sweep2d_band_kernel(int n1, int64_t n,
             T r_s[D];
             auto issue = [&](int s, int ixp) {
                 ixp = min(ixp, n1 - 1);
-                const T* Ar = Aline + (int64_t)ixp * nlo;
+                const T* Ar = Aline + (int64_t)ixp * ldl;
                 const int64_t rm = REV ? (mbase - ixp) : (mbase + ixp);
 #pragma unroll
                 for (int m = 0; m < MK; ++m) a_s[s][m] = Ar[kcl[m]];
@@ -640,6 +722,223 @@ __global__ void reset_kernel(unsigned* p, int count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
+// ------------------------------------------- factorisation, dataflow -----
+// Same recurrence as ilu_factor_kernel (left-looking rows of Alg. 2 with
+// U = D L^T), organised for latency:
+//   * Every row of L (n_lower entries, then 1/D(i)) is written exactly once
+//     into storage pre-filled with the sentinel, so each value is its own
+//     readiness flag. Gathers use ordinary cached loads; a sentinel (possibly
+//     a stale cached copy) sends the wave to coherent re-reads.
+//   * The lower offsets j of a row are visited in a dataflow order fixed on
+//     the host: a topological order of the in-row dependencies (u_k feeds
+//     u_j when offset(k) - offset(j) is a lower offset) that visits first
+//     the offsets whose rows finished longest ago. The loads of the next PD
+//     steps are in flight while a step is reduced.
+//   * The pivot accumulates u_j^2 / D(i + delta_j) step by step, so the row
+//     is complete right after its last step.
+//   * Each wave works on its own rows; the waves of a workgroup share the
+//     step and pair tables in LDS.
+template <int Q, int PD>
+__global__ __launch_bounds__(1024) void ilu_factor2_kernel(
+    int d, int n1, int64_t n, int nlo, int ldl, int nsteps, int npairs, int T, int h,
+    const int4* __restrict__ offs, const int4* __restrict__ steps, const int* __restrict__ sdxyz,
+    const unsigned* __restrict__ pairw, const int* __restrict__ row_order, const double* __restrict__ band,
+    const double* __restrict__ fold, double* __restrict__ LD, double* __restrict__ Dg,
+    double* __restrict__ invD, unsigned* ticket, int* flag) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    int4* st_s = (int4*)smem_raw;                 // [nsteps]
+    int4* of_s = st_s + nsteps;                   // [nlo + 1] offsets (dx, dy, dz, linear)
+    int* sd_s = (int*)(of_s + nlo + 1);           // [nsteps]
+    unsigned* pw_s = (unsigned*)(sd_s + nsteps);  // [npairs]
+    const size_t tab_bytes =
+        (((size_t)nsteps * 20 + (size_t)(nlo + 1) * 16 + (size_t)npairs * 4) + 15) & ~(size_t)15;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // per wave: u[0..nlo] (u[nlo] = M(i,i)), u[nlo+1] = 0, then w[0..nlo+1]
+    // (w[k] = 1/D(i + delta_k); w[nlo+1] absorbs the writes of padding steps)
+    double* u = (double*)(smem_raw + tab_bytes) + (size_t)wv * (2 * nlo + 4);
+    double* w = u + nlo + 2;
+    for (int e = tid; e < nsteps; e += blockDim.x) {
+        st_s[e] = steps[e];
+        sd_s[e] = sdxyz[e];
+    }
+    for (int e = tid; e <= nlo; e += blockDim.x) of_s[e] = offs[e];
+    for (int e = tid; e < npairs; e += blockDim.x) pw_s[e] = pairw[e];
+    __syncthreads();
+
+    const int W = 2 * h + 1;
+    const int T1 = T + 1;
+    const int bandT = n1 * W;
+    const int nzW = (d == 3) ? W : 1;
+    const int zoff = (int)(n * ldl);   // a row of zeros after the factor rows
+    // Control flow: the only lane-dependent branches sit in the middle of the
+    // row loop; the loop head and tail are wave-uniform (scalar tickets and
+    // pivots), so the compiler cannot turn a lane-0 block that straddles the
+    // back edge into a loop exit that leaves lane 0 behind.
+    unsigned tk0 = 0;
+    if (lane == 0) tk0 = atomicAdd(ticket, 1u);
+    unsigned tk = __builtin_amdgcn_readfirstlane(tk0);
+    while (tk < (unsigned)n) {
+        const int i = __builtin_amdgcn_readfirstlane(row_order[tk]);
+        const int ix = i % n1;
+        const int iy = (i / n1) % n1;
+        const int iz = (d == 3) ? i / (n1 * n1) : 0;
+        const int line = i / n1;
+        // M(i, i + delta_k) for the lower offsets and the diagonal (Sec. 4.2):
+        // sum_t S^(t)(ix, ix+dx) Fa_t + M^(t)(ix, ix+dx) Fb_t over the folded
+        // line coefficients; every address is valid (clamped), entries whose
+        // column leaves the grid are masked to zero.
+        {
+            const double* pS[Q];
+            const double* pF[Q];
+            double msk[Q], v[Q];
+#pragma unroll
+            for (int m = 0; m < Q; ++m) {
+                const int k = min(lane + 64 * m, nlo);
+                const int4 o = of_s[k];
+                const bool in = (lane + 64 * m <= nlo) && (unsigned)(ix + o.x) < (unsigned)n1 &&
+                                (unsigned)(iy + o.y) < (unsigned)n1 && (unsigned)(iz + o.z) < (unsigned)n1;
+                msk[m] = in ? 1.0 : 0.0;
+                pS[m] = band + ix * W + (o.x + h);
+                pF[m] = fold + ((int64_t)line * nzW * W + (int64_t)(d == 3 ? (o.z + h) * W : 0) + (o.y + h)) * 2 * T1;
+                v[m] = 0.0;
+            }
+            for (int t0 = 0; t0 < T1; t0 += 3) {
+                double bs[3][Q], bm[3][Q], fa[3][Q], fb[3][Q];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int t = min(t0 + c, T1 - 1);
+#pragma unroll
+                    for (int m = 0; m < Q; ++m) {
+                        bs[c][m] = pS[m][t * bandT];
+                        bm[c][m] = pS[m][(T1 + t) * bandT];
+                        fa[c][m] = pF[m][t];
+                        fb[c][m] = pF[m][T1 + t];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double on = (t0 + c < T1) ? 1.0 : 0.0;
+#pragma unroll
+                    for (int m = 0; m < Q; ++m) v[m] += on * (bs[c][m] * fa[c][m] + bm[c][m] * fb[c][m]);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < Q; ++m) {
+                const int k = lane + 64 * m;
+                if (k <= nlo) u[k] = v[m] * msk[m];
+                if (k < nlo + 2) w[k] = 0.0;
+            }
+            if (lane == 0) u[nlo + 1] = 0.0;
+        }
+
+        // Steps. Every step issues the same loads (a step whose row i+delta_j
+        // leaves the grid, or a padding step past the end, reads the zero row
+        // and leaves u_j = 0), so the load counter of each ring slot is static.
+        double g[PD][Q];
+        int kk[PD][Q], of[PD][Q];
+        double dv[PD], mj[PD];
+        int jj[PD], rof[PD];
+        auto issue = [&](int b, int s) {
+            const bool live = s < nsteps;
+            const int sc = live ? s : 0;
+            const int4 S = st_s[sc];
+            const int dd = sd_s[sc];
+            const int sj = __builtin_amdgcn_readfirstlane(S.x);
+            const int slin = __builtin_amdgcn_readfirstlane(S.y);
+            const int pb = __builtin_amdgcn_readfirstlane(S.z);
+            const int pe = __builtin_amdgcn_readfirstlane(S.w);
+            const int ddu = __builtin_amdgcn_readfirstlane(dd);
+            const int dx = (ddu & 0xFF) - 128, dy = ((ddu >> 8) & 0xFF) - 128, dz = ((ddu >> 16) & 0xFF) - 128;
+            const bool valid = live && (unsigned)(ix + dx) < (unsigned)n1 && (unsigned)(iy + dy) < (unsigned)n1 &&
+                               (unsigned)(iz + dz) < (unsigned)n1;
+            jj[b] = live ? sj : nlo + 1;
+            const int r0 = (i + slin) * ldl;
+            unsigned wd[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int p = pb + lane + 64 * q;
+                wd[q] = pw_s[(p < pe) ? p : 0];
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const bool act = valid && (pb + lane + 64 * q < pe);
+                kk[b][q] = act ? (int)(wd[q] & 0xFFFFu) : nlo + 1;
+                of[b][q] = act ? r0 + (int)(wd[q] >> 16) : zoff;
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                g[b][q] = __hip_atomic_load(LD + of[b][q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            rof[b] = valid ? r0 + nlo : zoff;
+            dv[b] = __hip_atomic_load(LD + rof[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            mj[b] = u[jj[b]];   // M(i, i+delta_j) (0 when invalid); u_j is written only by step j
+        };
+        double piv = 0.0;
+        auto consume = [&](int b) {
+            bool bad = Sentinel<double>::is(dv[b]);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) bad |= Sentinel<double>::is(g[b][q]);
+            if (__builtin_expect(__any(bad), 0)) {
+                // the last steps of a row wait here for the rows one level
+                // back; poll at a fixed short interval (each coherent load is
+                // itself a round trip) so the row starts as soon as they land
+                for (;;) {
+                    bool still = false;
+                    if (Sentinel<double>::is(dv[b])) {
+                        dv[b] = ld_coh(LD + rof[b]);
+                        still |= Sentinel<double>::is(dv[b]);
+                    }
+#pragma unroll
+                    for (int q = 0; q < Q; ++q)
+                        if (Sentinel<double>::is(g[b][q])) {
+                            g[b][q] = ld_coh(LD + of[b][q]);
+                            still |= Sentinel<double>::is(g[b][q]);
+                        }
+                    if (!__any(still)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc += u[kk[b][q]] * g[b][q];
+            acc = wave_sum_dpp(acc);
+            const double uj = mj[b] - acc;
+            if (lane == 0) {
+                u[jj[b]] = uj;
+                w[jj[b]] = dv[b];
+            }
+            piv += uj * uj * dv[b];
+        };
+#pragma unroll
+        for (int b = 0; b < PD; ++b) issue(b, b);
+        // next row, fetched while this row's first loads are in flight
+        unsigned tkn = 0;
+        if (lane == 0) tkn = atomicAdd(ticket, 1u);
+        for (int s0 = 0; s0 < nsteps; s0 += PD) {
+#pragma unroll
+            for (int b = 0; b < PD; ++b) {
+                consume(b);
+                issue(b, s0 + b + PD);
+            }
+        }
+        // L(i, i+delta_k) = u_k / D(i+delta_k); D(i) = M(i,i) - sum_k u_k L(i, i+delta_k).
+        // D(i) is the same in every lane; taking it from lane 0 makes the
+        // pivot test and the stores below wave-uniform.
+        const double Dr = u[nlo] - piv;
+        const double Dii = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(Dr)),
+                                            __builtin_amdgcn_readfirstlane(__double2loint(Dr)));
+        const double iv = 1.0 / Dii;
+        double* Li = LD + (int64_t)i * ldl;
+        for (int k = lane; k <= nlo; k += 64)
+            st_coh(Li + k, Sentinel<double>::clean(k < nlo ? u[k] * w[k] : iv));
+        Dg[i] = Dii;    // the same value from every lane
+        invD[i] = iv;
+        if (!(Dii > 0.0) || !isfinite(Dii)) atomicOr(flag, 1);   // uniform branch; one atomic per lane, rare
+        tk = __builtin_amdgcn_readfirstlane(tkn);
+    }
+}
+
 // ------------------------------------------------------------- host ------
 static int persistent_grid(const void* kernel, int block, size_t shmem, int64_t units) {
     int dev = 0, cus = 256, per = 1;
@@ -653,23 +952,37 @@ static int persistent_grid(const void* kernel, int block, size_t shmem, int64_t 
     return (int)g;
 }
 
+// Host tables whose contents are copied to the device with hipMemcpyAsync;
+// they must stay alive until the stream has executed the copies.
+struct FactorHostTables {
+    std::vector<int> off4, ptr, pk, pl, st4, sd, lines, lstart, runs;
+    std::vector<unsigned> pw;
+};
+
+static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& H);
+
 lgp_status factor_build(Factor& F, hipStream_t s) {
+    FactorHostTables H;
+    lgp_status st = factor_build_impl(F, s, H);
+    // drain the stream before H goes away, on success and on failure alike
+    if (hipStreamSynchronize(s) != hipSuccess && st == LGP_OK) st = LGP_E_HIP;
+    return st;
+}
+
+static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& H) {
     const int d = F.d, n1 = F.n1, T = F.T, h = F.h;
     const int W = 2 * h + 1, T1 = T + 1;
     const int64_t n = F.n;
     // 1D band tables S^(t)(i, i+delta), M^(t)(i, i+delta)
-    std::vector<double> band((size_t)2 * T1 * n1 * W, 0.0);
-    for (int t = 0; t <= T; ++t)
-        for (int i = 0; i < n1; ++i)
-            for (int dl = -h; dl <= h; ++dl) {
-                const int m = i + dl;
-                if (m < 0 || m >= n1) continue;
-                band[((size_t)t * n1 + i) * W + (dl + h)] = S1(t, i, m);
-                band[((size_t)(T1 + t) * n1 + i) * W + (dl + h)] = M1(t, i, m);
-            }
-    LGP_HIP(hipMemcpyAsync(F.band, band.data(), band.size() * 8, hipMemcpyHostToDevice, s));
+    {
+        const int64_t total = (int64_t)T1 * n1 * W;
+        hipLaunchKernelGGL(band_kernel, dim3((unsigned)std::min<int64_t>(4096, (total + 255) / 256)), dim3(256), 0,
+                           s, T, n1, h, F.band);
+        LGP_CHECK_LAUNCH();
+    }
     // offsets (lower + diagonal) with linear offsets
-    std::vector<int> off4((size_t)4 * (F.nlo + 1));
+    std::vector<int>& off4 = H.off4;
+    off4.assign((size_t)4 * (F.nlo + 1), 0);
     for (int k = 0; k <= F.nlo; ++k) {
         const int* o = &F.offs[3 * k];
         off4[4 * k + 0] = o[0];
@@ -680,7 +993,8 @@ lgp_status factor_build(Factor& F, hipStream_t s) {
     LGP_HIP(hipMemcpyAsync(F.d_offs, off4.data(), off4.size() * 4, hipMemcpyHostToDevice, s));
     // left-looking pair lists: for lower j, all lower k < j with
     // offset(k) - offset(j) in the lower list (and its index)
-    std::vector<int> ptr(F.nlo + 2, 0), pk, pl;
+    std::vector<int>&ptr = H.ptr, &pk = H.pk, &pl = H.pl;
+    ptr.assign(F.nlo + 2, 0);
     {
         const int R = 4 * h + 1;
         std::vector<int> lut((size_t)R * R * R, -1);
@@ -704,13 +1018,68 @@ lgp_status factor_build(Factor& F, hipStream_t s) {
         ptr[F.nlo + 1] = (int)pk.size();
     }
     if ((int)pk.size() != F.npairs) return LGP_E_ARG;   // planner and builder disagree
+    F.maxpairs = 0;
+    for (int j = 0; j < F.nlo; ++j) F.maxpairs = std::max(F.maxpairs, ptr[j + 1] - ptr[j]);
+    // Dataflow order of the lower offsets for the factorisation: a topological
+    // order of "u_k feeds u_j" (k in the pair list of j) that prefers the
+    // offsets whose rows lie most hyperplane levels back.
+    {
+        const int64_t A1 = F.Hx + 1, B1 = (int64_t)(F.Hx + 1) * (F.Hy + 1);
+        std::vector<int64_t> lag(F.nlo);
+        for (int k = 0; k < F.nlo; ++k)
+            lag[k] = -((int64_t)F.offs[3 * k] + A1 * F.offs[3 * k + 1] + B1 * F.offs[3 * k + 2]);
+        std::vector<int> indeg(F.nlo, 0), sptr(F.nlo + 1, 0), succ(pk.size());
+        for (int j = 0; j < F.nlo; ++j) indeg[j] = ptr[j + 1] - ptr[j];
+        for (size_t e = 0; e < pk.size(); ++e) sptr[pk[e] + 1]++;
+        for (int k = 0; k < F.nlo; ++k) sptr[k + 1] += sptr[k];
+        {
+            std::vector<int> fill(sptr.begin(), sptr.end() - 1);
+            for (int j = 0; j < F.nlo; ++j)
+                for (int e = ptr[j]; e < ptr[j + 1]; ++e) succ[fill[pk[e]]++] = j;
+        }
+        auto later = [&](int a, int b) { return lag[a] != lag[b] ? lag[a] < lag[b] : a > b; };
+        std::vector<int> heap, order;
+        for (int j = 0; j < F.nlo; ++j)
+            if (indeg[j] == 0) heap.push_back(j);
+        std::make_heap(heap.begin(), heap.end(), later);
+        while (!heap.empty()) {
+            std::pop_heap(heap.begin(), heap.end(), later);
+            const int k = heap.back();
+            heap.pop_back();
+            order.push_back(k);
+            for (int e = sptr[k]; e < sptr[k + 1]; ++e)
+                if (--indeg[succ[e]] == 0) {
+                    heap.push_back(succ[e]);
+                    std::push_heap(heap.begin(), heap.end(), later);
+                }
+        }
+        if ((int)order.size() != F.nlo) return LGP_E_ARG;
+        std::vector<int>&st4 = H.st4, &sd = H.sd;
+        std::vector<unsigned>& pw = H.pw;
+        st4.assign((size_t)4 * (F.nlo + 1), 0);
+        sd.assign(F.nlo + 1, 0);
+        pw.reserve(pk.size());
+        for (int s2 = 0; s2 < F.nlo; ++s2) {
+            const int j = order[s2];
+            st4[4 * s2 + 0] = j;
+            st4[4 * s2 + 1] = off4[4 * j + 3];
+            st4[4 * s2 + 2] = (int)pw.size();
+            for (int e = ptr[j]; e < ptr[j + 1]; ++e) pw.push_back((unsigned)pk[e] | ((unsigned)pl[e] << 16));
+            st4[4 * s2 + 3] = (int)pw.size();
+            sd[s2] = (F.offs[3 * j] + 128) | ((F.offs[3 * j + 1] + 128) << 8) | ((F.offs[3 * j + 2] + 128) << 16);
+        }
+        LGP_HIP(hipMemcpyAsync(F.steps, st4.data(), st4.size() * 4, hipMemcpyHostToDevice, s));
+        LGP_HIP(hipMemcpyAsync(F.sdxyz, sd.data(), sd.size() * 4, hipMemcpyHostToDevice, s));
+        if (!pw.empty()) LGP_HIP(hipMemcpyAsync(F.pairw, pw.data(), pw.size() * 4, hipMemcpyHostToDevice, s));
+    }
     LGP_HIP(hipMemcpyAsync(F.pair_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, s));
     if (F.npairs > 0) {
         LGP_HIP(hipMemcpyAsync(F.pair_j, pk.data(), pk.size() * 4, hipMemcpyHostToDevice, s));
         LGP_HIP(hipMemcpyAsync(F.pair_l, pl.data(), pl.size() * 4, hipMemcpyHostToDevice, s));
     }
     // line order for the sweeps: key iy + (Hy+1) iz
-    std::vector<int> lines(F.nlines);
+    std::vector<int>& lines = H.lines;
+    lines.resize(F.nlines);
     for (int l = 0; l < F.nlines; ++l) lines[l] = l;
     std::stable_sort(lines.begin(), lines.end(), [&](int a, int b) {
         const int ka = (a % n1) + (F.Hy + 1) * (a / n1), kb = (b % n1) + (F.Hy + 1) * (b / n1);
@@ -718,52 +1087,117 @@ lgp_status factor_build(Factor& F, hipStream_t s) {
     });
     LGP_HIP(hipMemcpyAsync(F.line_order, lines.data(), lines.size() * 4, hipMemcpyHostToDevice, s));
     // row order for the factorisation: level ix + (Hx+1) iy + (Hx+1)(Hy+1) iz.
-    // The order and the per-line folded coefficients live in the Ut buffer
-    // (not yet needed) to avoid extra storage.
+    // Each grid line covers the consecutive levels base .. base+n1-1, so the
+    // level sizes come from the lines alone; the rows are placed on the
+    // device. The order and the per-line folded coefficients live in the Ut
+    // buffer (not yet needed) to avoid extra storage.
     const int64_t A1 = F.Hx + 1, B1 = (int64_t)(F.Hx + 1) * (F.Hy + 1);
     const int64_t maxlev = (n1 - 1) * (1 + A1 + (d == 3 ? B1 : 0)) + 1;
+    if (maxlev > F.maxlev) return LGP_E_ARG;   // planner and builder disagree
     F.levels = (int)maxlev;
-    std::vector<int> cnt(maxlev + 1, 0);
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t lv = (i % n1) + A1 * ((i / n1) % n1) + (d == 3 ? B1 * (i / ((int64_t)n1 * n1)) : 0);
-        cnt[lv + 1]++;
-    }
-    for (int64_t l = 0; l < maxlev; ++l) cnt[l + 1] += cnt[l];
-    std::vector<int> order(n);
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t lv = (i % n1) + A1 * ((i / n1) % n1) + (d == 3 ? B1 * (i / ((int64_t)n1 * n1)) : 0);
-        order[cnt[lv]++] = (int)i;
+    std::vector<int>& lstart = H.lstart;
+    lstart.assign(2 * maxlev + 2, 0);
+    {
+        std::vector<int> diff(maxlev + 1, 0);
+        const int nlz = (d == 3) ? n1 : 1;
+        for (int iz = 0; iz < nlz; ++iz)
+            for (int iy = 0; iy < n1; ++iy) {
+                const int64_t b0 = A1 * iy + B1 * iz;
+                diff[b0] += 1;
+                diff[b0 + n1] -= 1;
+            }
+        int run = 0, acc = 0;
+        for (int64_t l = 0; l < maxlev; ++l) {
+            run += diff[l];
+            lstart[l] = acc;
+            acc += run;
+        }
+        lstart[maxlev] = acc;
+        if (acc != n) return LGP_E_ARG;
     }
     int* d_order = (int*)F.Ut;
     double* fold = (double*)((char*)F.Ut + (((size_t)n * 4 + 255) & ~(size_t)255));
     const int nzW = (d == 3) ? W : 1;
     const size_t fold_bytes = (size_t)F.nlines * nzW * W * 2 * T1 * 8;
-    if ((((size_t)n * 4 + 255) & ~(size_t)255) + fold_bytes > (size_t)n * F.nlo * 8) {
-        // small grids: the Ut buffer is too small for the scratch; use L32 if present
+    if ((((size_t)n * 4 + 255) & ~(size_t)255) + fold_bytes > (size_t)n * F.ldl * 8) {
+        // small grids: the Ut buffer is too small for the scratch
         return LGP_E_UNSUPPORTED;
     }
-    LGP_HIP(hipMemcpyAsync(d_order, order.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(F.lev, lstart.data(), lstart.size() * 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(level_order_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, s,
+                       d, n1, n, (int)A1, (int)B1, (const int*)F.lev, F.lev + maxlev + 1, d_order);
+    LGP_CHECK_LAUNCH();
     hipLaunchKernelGGL(fold_kernel, dim3(std::min(F.nlines, 4096)), dim3(256), 0, s, d, n1, T, h,
                        (const double*)F.band, (const double*)F.coefA, (const double*)F.coefB, fold, F.nlines);
     LGP_CHECK_LAUNCH();
-    // done flags live in the y_tmp buffer (n doubles >= n unsigned)
-    unsigned* done = (unsigned*)F.y_tmp;
-    LGP_HIP(hipMemsetAsync(done, 0, (size_t)n * 4, s));
     LGP_HIP(hipMemsetAsync(F.ticket, 0, 16, s));
     LGP_HIP(hipMemsetAsync(F.flag, 0, 16, s));
-    const size_t shmem = (size_t)(F.nlo + 1) * 8;
-    const int grid = persistent_grid((const void*)ilu_factor_kernel, 64, shmem, n);
-    hipLaunchKernelGGL(ilu_factor_kernel, dim3(grid), dim3(64), shmem, s, d, n1, n, F.nlo, T, h,
-                       (const int4*)F.d_offs, (const int*)d_order, (const double*)F.band, (const double*)fold,
-                       (const int*)F.pair_ptr, (const int*)F.pair_j, (const int*)F.pair_l, F.L, F.Dg, F.invD,
-                       done, F.ticket, F.flag);
-    LGP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(build_ut_kernel, dim3(4096), dim3(256), 0, s, d, n1, n, F.nlo, (const int4*)F.d_offs,
-                       (const double*)F.L, F.Ut);
+    LGP_HIP(hipMemsetAsync(F.L + (size_t)n * F.ldl, 0, (size_t)F.ldl * 8, s));   // zero row
+    // dataflow kernel: pair table in LDS, at most 64*Q pairs per step, 32-bit
+    // element offsets, pair indices in 16 bits
+    constexpr int FQ = 4, FPD = 4;
+    const size_t tab_bytes =
+        (((size_t)F.nlo * 20 + (size_t)(F.nlo + 1) * 16 + (size_t)F.npairs * 4) + 15) & ~(size_t)15;
+    const size_t wave_bytes = (size_t)(2 * F.nlo + 4) * 8;
+    int wpb = 16;
+    while (wpb > 4 && tab_bytes + wpb * wave_bytes > 150 * 1024) wpb /= 2;
+    const bool dataflow = F.maxpairs <= 64 * FQ && F.nlo + 1 <= 64 * FQ &&
+                          (int64_t)(n + 1) * F.ldl < (int64_t)INT32_MAX &&
+                          tab_bytes + wpb * wave_bytes <= 150 * 1024;
+    if (dataflow) {
+        hipLaunchKernelGGL(fill_sentinel_kernel<double>, dim3(std::min<int64_t>(8192, (n * F.ldl + 255) / 256)),
+                           dim3(256), 0, s, (int64_t)n * F.ldl, F.L, (const int*)nullptr);
+        LGP_CHECK_LAUNCH();
+        auto kf = ilu_factor2_kernel<FQ, FPD>;
+        const size_t shmem = tab_bytes + wpb * wave_bytes;
+        hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        const int grid = persistent_grid((const void*)kf, 64 * wpb, shmem, (n + wpb - 1) / wpb);
+        hipLaunchKernelGGL(kf, dim3(grid), dim3(64 * wpb), shmem, s, d, n1, n, F.nlo, F.ldl, F.nlo, F.npairs, T, h,
+                           (const int4*)F.d_offs, (const int4*)F.steps, (const int*)F.sdxyz,
+                           (const unsigned*)F.pairw, (const int*)d_order, (const double*)F.band,
+                           (const double*)fold, F.L, F.Dg, F.invD, F.ticket, F.flag);
+        LGP_CHECK_LAUNCH();
+    } else {
+        // done flags live in the y_tmp buffer (n doubles >= n unsigned)
+        unsigned* done = (unsigned*)F.y_tmp;
+        LGP_HIP(hipMemsetAsync(done, 0, (size_t)n * 4, s));
+        const size_t shmem = (size_t)(F.nlo + 1) * 8;
+        const int grid = persistent_grid((const void*)ilu_factor_kernel, 64, shmem, n);
+        hipLaunchKernelGGL(ilu_factor_kernel, dim3(grid), dim3(64), shmem, s, d, n1, n, F.nlo, F.ldl, T, h,
+                           (const int4*)F.d_offs, (const int*)d_order, (const double*)F.band, (const double*)fold,
+                           (const int*)F.pair_ptr, (const int*)F.pair_j, (const int*)F.pair_l, F.L, F.Dg,
+                           F.invD, done, F.ticket, F.flag);
+        LGP_CHECK_LAUNCH();
+    }
+    // runs of lower offsets with equal (dy, dz)
+    std::vector<int>& runs = H.runs;
+    int maxK = 0, maxspan = 0;
+    for (int k = 0; k < F.nlo;) {
+        int e = k + 1;
+        while (e < F.nlo && F.offs[3 * e + 1] == F.offs[3 * k + 1] && F.offs[3 * e + 2] == F.offs[3 * k + 2]) ++e;
+        runs.insert(runs.end(), {k, e, F.offs[3 * k], F.offs[3 * (e - 1)]});
+        maxK = std::max(maxK, e - k);
+        maxspan = std::max(maxspan, F.offs[3 * (e - 1)] - F.offs[3 * k]);
+        k = e;
+    }
+    F.nruns = (int)runs.size() / 4;
+    int R = 256;
+    while (R > 16 && (size_t)(R + maxspan) * maxK * 8 > 64 * 1024) R /= 2;
+    if (F.nruns > 0 && (size_t)(R + maxspan) * maxK * 8 <= 64 * 1024) {
+        LGP_HIP(hipMemcpyAsync(F.runs, runs.data(), runs.size() * 4, hipMemcpyHostToDevice, s));
+        const size_t shmem = (size_t)(R + maxspan) * maxK * 8;
+        hipFuncSetAttribute((const void*)build_ut_tiled_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shmem);
+        hipLaunchKernelGGL(build_ut_tiled_kernel, dim3((unsigned)((n + R - 1) / R), F.nruns), dim3(256), shmem, s, d,
+                           n1, n, F.ldl, (const int4*)F.d_offs, (const int4*)F.runs, R, (const double*)F.L, F.Ut);
+    } else {
+        hipLaunchKernelGGL(build_ut_kernel, dim3(4096), dim3(256), 0, s, d, n1, n, F.nlo, F.ldl,
+                           (const int4*)F.d_offs, (const double*)F.L, F.Ut);
+    }
     LGP_CHECK_LAUNCH();
     if (F.has32) {
-        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.nlo, (const double*)F.L, F.L32);
-        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.nlo, (const double*)F.Ut, F.Ut32);
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.ldl, (const double*)F.L, F.L32);
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.ldl, (const double*)F.Ut, F.Ut32);
         hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n, (const double*)F.invD, F.invD32);
         LGP_CHECK_LAUNCH();
     }
@@ -789,7 +1223,8 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
         auto pick = [&](auto kf) {
             hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)band_shmem);
             const int grid = persistent_grid((const void*)kf, 64 * BB, band_shmem, nbands);
-            hipLaunchKernelGGL(kf, dim3(grid), dim3(64 * BB), band_shmem, s, F.n1, n, F.nlo, (const int4*)F.d_offs,
+            hipLaunchKernelGGL(kf, dim3(grid), dim3(64 * BB), band_shmem, s, F.n1, n, F.nlo, F.ldl,
+                               (const int4*)F.d_offs,
                                A, scale, in, out, tick, stop, F.Hx, F.Hy);
         };
         if (F.nlo <= 128) {
@@ -805,13 +1240,13 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
     } else if (F.d == 2) {
         auto kf = backward ? sweep_kernel<T, 64, true, true> : sweep_kernel<T, 64, false, false>;
         const int grid = persistent_grid((const void*)kf, 64, 0, F.nlines);
-        hipLaunchKernelGGL(kf, dim3(grid), dim3(64), 0, s, F.d, F.n1, n, F.nlo, (const int4*)F.d_offs,
+        hipLaunchKernelGGL(kf, dim3(grid), dim3(64), 0, s, F.d, F.n1, n, F.nlo, F.ldl, (const int4*)F.d_offs,
                            (const int*)F.line_order, F.nlines, F.Hx, F.Hy, A, scale, in, out, prog, tick,
                            stop);
     } else {
         auto kf = backward ? sweep_kernel<T, 256, true, true> : sweep_kernel<T, 256, false, false>;
         const int grid = persistent_grid((const void*)kf, 256, 0, F.nlines);
-        hipLaunchKernelGGL(kf, dim3(grid), dim3(256), 0, s, F.d, F.n1, n, F.nlo, (const int4*)F.d_offs,
+        hipLaunchKernelGGL(kf, dim3(grid), dim3(256), 0, s, F.d, F.n1, n, F.nlo, F.ldl, (const int4*)F.d_offs,
                            (const int*)F.line_order, F.nlines, F.Hx, F.Hy, A, scale, in, out, prog, tick,
                            stop);
     }

@@ -93,13 +93,14 @@ struct Factor {
     int d, n1, Ta, Tb, T, h;   // h = reach of the pattern per direction
     int64_t n;
     int noff, nlo;             // pattern size, number of strictly lower offsets
+    int ldl;                   // row stride of L / Ut (>= nlo + 1, multiple of 16 doubles)
     std::vector<int> offs;     // host, 3*noff
     int Hx, Hy, Hz;            // max |offset| per direction
     int nlines;                // lines of constant (y,z)
     int levels;
     // device
-    double* L;        // [n][nlo]
-    double* Ut;       // [n][nlo]  backward-sweep operator in reversed order
+    double* L;        // [n+1][ldl]: L(i, i+delta_k) at k < nlo, 1/D(i) at nlo; row n is zero
+    double* Ut;       // [n][ldl]  backward-sweep operator in reversed order
     double* Dg;       // [n] pivots
     double* invD;     // [n]
     float* L32; float* Ut32; float* invD32;   // optional FP32 copies
@@ -115,6 +116,14 @@ struct Factor {
     int* pair_j;      // [npairs] j index (lower offset index, or nlo for the diagonal)
     int* pair_l;      // [npairs] index of offset(k) - offset(j) in the lower list
     int npairs;
+    int maxpairs;     // largest pair list of one lower offset
+    int* steps;       // [nlo][4] {j, linear offset, first pair, end pair} in dataflow order
+    int* sdxyz;       // [nlo] packed (dx+128) | (dy+128) << 8 | (dz+128) << 16 of each step
+    unsigned* pairw;  // [npairs] k | l << 16, grouped by step
+    int maxlev;       // number of hyperplane levels
+    int* lev;         // [maxlev + 1] first ticket of each level, then [maxlev] fill counters
+    int* runs;        // [nruns][4] runs of lower offsets with equal (dy, dz): {kb, ke, dx_first, dx_last}
+    int nruns;
     double* y_tmp;    // [n] intermediate of precond_apply
     bool has32;
     size_t bytes;
@@ -136,6 +145,6 @@ lgp_status setup_nodes(Problem& P, const double* a, const double* b, hipStream_t
 
 // host helpers
 void gauss_legendre_host(int N, std::vector<double>& x, std::vector<double>& w);
-double triple_legendre(int t, int m, int n);   // int L_t L_m L_n over (-1,1)
+__host__ __device__ double triple_legendre(int t, int m, int n);   // int L_t L_m L_n over (-1,1)
 
 }  // namespace lgp

@@ -120,11 +120,12 @@ class Factor:
         dsc = lgpcg.FactorDesc()
         check(lib().lgp_factor_describe(self.handle, ctypes.byref(dsc)), "lgp_factor_describe")
         offs = [(dsc.offsets[3 * k], dsc.offsets[3 * k + 1], dsc.offsets[3 * k + 2]) for k in range(dsc.noff)]
-        n, nlo = dsc.n, dsc.n_lower
+        n, nlo, ld = dsc.n, dsc.n_lower, dsc.ld
         base = self.buf.data_ptr()
-        Lv = self.buf[dsc.L - base: dsc.L - base + n * nlo * 8].view(torch.float64).view(n, nlo)
+        rows = self.buf[dsc.L - base: dsc.L - base + n * ld * 8].view(torch.float64).view(n, ld)
         Dv = self.buf[dsc.D - base: dsc.D - base + n * 8].view(torch.float64)
-        return dict(offsets=offs, n_lower=nlo, L=Lv, D=Dv, levels=dsc.levels, n=n)
+        return dict(offsets=offs, n_lower=nlo, ld=ld, L=rows[:, :nlo], invD=rows[:, nlo], D=Dv,
+                    levels=dsc.levels, n=n)
 
 
 def pcg_solve(problem: Problem, factor: Factor, F: torch.Tensor, x: torch.Tensor = None, rtol: float = 1e-10,

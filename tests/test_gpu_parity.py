@@ -112,6 +112,7 @@ def test_factor_and_sweeps(d, N, Ta, Tb, seed):
     Do = st.H[:, nlo]
     assert np.max(np.abs(Lg - Lo)) <= 1e-12 * max(1.0, np.max(np.abs(Lo)))
     assert np.max(np.abs(Dg - Do)) <= 1e-12 * np.max(np.abs(Do))
+    assert np.max(np.abs(_host(desc["invD"]) * Do - 1.0)) <= 1e-12
     r = synth.random_vector((N - 1) ** d, 5)
     y_ref = st.forward(r)
     y = _host(Fc.forward(_dev(r)))
