@@ -143,7 +143,9 @@ typedef struct {
     lgp_dtype inner;     /* LGP_F64: plain PCG. LGP_F32 / LGP_BF16: FP64 iterative
                             refinement around an inner PCG whose matvec runs in that
                             precision and whose sweeps use FP32 factors */
-    double inner_rtol;   /* inner stop rule in mixed mode; default 1e-4 */
+    double inner_rtol;   /* inner stop rule in mixed mode; <= 0 selects the default:
+                            1e-3 for LGP_F32, 1e-1 for LGP_BF16 (a BF16 operator is
+                            accurate to about 1e-2, and a tighter inner rule stalls) */
     int max_outer;       /* refinement steps in mixed mode; default 60 */
     int check_every;     /* iterations enqueued between host convergence checks; default 4 */
 } lgp_solve_opts;

@@ -375,17 +375,20 @@ lgp_status lgp_pcg_solve(lgp_problem p, lgp_factor m, const double* F, double* x
     o.rtol = 1e-10;
     o.max_iter = 2000;
     o.inner = LGP_F64;
-    o.inner_rtol = 1e-4;
+    o.inner_rtol = 0.0;
     o.max_outer = 60;
     o.check_every = 4;
     if (opts) {
         o = *opts;
         if (!(o.rtol > 0.0)) return LGP_E_ARG;
         if (o.max_iter <= 0) o.max_iter = 2000;
-        if (!(o.inner_rtol > 0.0)) o.inner_rtol = 1e-4;
         if (o.max_outer <= 0) o.max_outer = 60;
         if (o.check_every <= 0) o.check_every = 4;
     }
+    // an inner solve only has to gain what its operator's precision allows:
+    // BF16 products are accurate to about 1e-2, so asking the inner PCG for
+    // more makes it stall; FP32 ones to about 1e-6
+    if (!(o.inner_rtol > 0.0)) o.inner_rtol = (o.inner == LGP_BF16) ? 1e-1 : 1e-3;
     lgp_status st = pcg_solve_impl(p->P, m->F, F, x, o, ws, ws_bytes, (hipStream_t)stream, info);
     info->status = st;
     return st;

@@ -129,7 +129,7 @@ class Factor:
 
 
 def pcg_solve(problem: Problem, factor: Factor, F: torch.Tensor, x: torch.Tensor = None, rtol: float = 1e-10,
-              max_iter: int = 2000, inner: str = "f64", inner_rtol: float = 1e-4, max_outer: int = 60,
+              max_iter: int = 2000, inner: str = "f64", inner_rtol: float = 0.0, max_outer: int = 60,
               check_every: int = 4, ws: torch.Tensor = None, raise_on_error: bool = True):
     """Solve K x = F by PCG (Alg. 1) with the one-step ILU(0) preconditioner.
     Returns (x, info dict). `x` is used as the initial guess (zeros if None)."""
