@@ -553,6 +553,137 @@ __device__ inline void backoff(int& nap) {
     if (nap < 64) nap <<= 1;
 }
 
+// One line of a band: wave w of the workgroup walks grid line L = first + w.
+// STAGE: this wave also stages the Hy lines preceding the band (wave 0 of
+// every band but the first). LAST: this line is read by the next band, so
+// every value goes to device memory at once. Both are fixed for the whole
+// walk, so every path through a row issues the same vector memory operations
+// (all lanes load and store, idle lanes on valid dummy addresses or the same
+// value); the compiler can then keep the prefetches of later rows in flight
+// instead of draining them at merges of paths with different counts.
+template <typename T, int MK, int D, bool REV, bool SCALE, bool STAGE, bool LAST>
+__device__ inline void band_line(int n1, int64_t n, int ldl, int L, int first, int lbase, int Hx, int Hy,
+                                 const int (&ody)[MK], const int (&odx)[MK], const int (&kcl)[MK],
+                                 const bool (&oval)[MK], const T* __restrict__ A, const T* __restrict__ scale,
+                                 const T* __restrict__ in, T* __restrict__ out, T* lb, int w, int zslot) {
+    const int lane = threadIdx.x & 63;
+    const int64_t rowbase = (int64_t)L * n1;
+    const int64_t mbase = REV ? (n - 1 - rowbase) : rowbase;
+    const T* Aline = A + rowbase * ldl;
+    int loff[MK];
+    bool lok[MK];
+#pragma unroll
+    for (int m = 0; m < MK; ++m) {
+        const int ly = L + ody[m];
+        lok[m] = oval[m] && ly >= 0 && ly < n1;
+        loff[m] = lok[m] ? (ly - lbase) * n1 + odx[m] : 0;
+    }
+    T a_s[D][MK];
+    T r_s[D];
+    auto issue = [&](int s, int ixp) {
+        ixp = min(ixp, n1 - 1);
+        const T* Ar = Aline + (int64_t)ixp * ldl;
+        const int64_t rm = REV ? (mbase - ixp) : (mbase + ixp);
+#pragma unroll
+        for (int m = 0; m < MK; ++m) a_s[s][m] = Ar[kcl[m]];
+        // vector loads (a relaxed atomic is never turned into a scalar
+        // load; scalar loads share lgkmcnt with LDS)
+        T rv = __hip_atomic_load(&in[rm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (SCALE) rv *= __hip_atomic_load(&scale[rm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        r_s[s] = rv;
+    };
+    // staging lanes 0..Hy-1 (lines lbase..first-1 that exist)
+    const bool stager = STAGE && (lane < Hy) && (lbase + lane >= 0);
+    const int sline = stager ? lbase + lane : 0;
+    auto saddr = [&](int x) {
+        x = min(x, n1 - 1);
+        const int64_t rp = (int64_t)sline * n1 + x;
+        return REV ? (n - 1 - rp) : rp;
+    };
+    T st_v[D];
+    // stage column x (value v loaded earlier; re-read while not ready)
+    auto stage_now = [&](int x, T v) {
+        const bool act = stager && x < n1;
+        if (__builtin_expect(__any(act && Sentinel<T>::is(v)), 0)) {
+            while (act && Sentinel<T>::is(v)) {
+                __builtin_amdgcn_s_sleep(1);
+                v = ld_coh(&out[saddr(x)]);
+            }
+        }
+        if (act) lb[lane * n1 + x] = v;
+    };
+    if (STAGE) {
+        for (int x = 0; x < Hx && x < n1; ++x) stage_now(x, ld_coh(&out[saddr(x)]));
+#pragma unroll
+        for (int s = 0; s < D; ++s) st_v[s] = ld_coh(&out[saddr(Hx + s)]);
+    }
+    auto row = [&](int s, int ix) -> T {
+        if (STAGE) {
+            const int x = ix + Hx;
+            stage_now(x, st_v[s]);
+            st_v[s] = ld_coh(&out[saddr(x + D)]);
+        }
+        int idx[MK];
+#pragma unroll
+        for (int m = 0; m < MK; ++m) {
+            const bool ok = lok[m] && (unsigned)(ix + odx[m]) < (unsigned)n1;
+            idx[m] = ok ? loff[m] + ix : zslot;
+        }
+        T yv[MK];
+#pragma unroll
+        for (int m = 0; m < MK; ++m) yv[m] = lb[idx[m]];
+        bool miss = false;
+#pragma unroll
+        for (int m = 0; m < MK; ++m) miss |= Sentinel<T>::is(yv[m]);
+        if (__builtin_expect(__any(miss), 0)) {
+#pragma unroll
+            for (int m = 0; m < MK; ++m) {
+                while (Sentinel<T>::is(yv[m])) {
+                    __builtin_amdgcn_s_sleep(1);
+                    yv[m] = __hip_atomic_load(&lb[idx[m]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+        }
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < MK; ++m) acc += (idx[m] == zslot ? T(0) : a_s[s][m]) * yv[m];
+        return wave_sum_dpp(acc);
+    };
+    T* lbw = lb + (Hy + w) * n1;
+    auto mrow = [&](int ixp) { return REV ? (mbase - ixp) : (mbase + ixp); };
+#pragma unroll
+    for (int s = 0; s < D; ++s) issue(s, s);
+    int ix0 = 0;
+    for (; ix0 + D <= n1; ix0 += D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            const int ix = ix0 + s;
+            const T acc = row(s, ix);
+            const T y = Sentinel<T>::clean(r_s[s] - acc);
+            issue(s, ix + D);
+            if (lane == 0) lbw[ix] = y;
+            if (LAST) st_coh(&out[mrow(ix)], y);   // every lane, the same value
+        }
+        if (!LAST) {
+            // the group's values from LDS; lanes beyond D repeat them
+            wait_lds();
+            const int j = ix0 + (lane % D);
+            st_coh(&out[mrow(j)], lbw[j]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+        const int ix = ix0 + s;
+        if (ix < n1) {
+            const T acc = row(s, ix);
+            const T y = Sentinel<T>::clean(r_s[s] - acc);
+            if (lane == 0) lbw[ix] = y;
+        }
+    }
+    wait_lds();
+    if (lane < n1 - ix0) st_coh(&out[mrow(ix0 + lane)], lbw[ix0 + lane]);
+}
+
 template <typename T, int MK, int D, int B, bool REV, bool SCALE>
 __global__ __launch_bounds__(64 * B) void sweep2d_band_kernel(int n1, int64_t n, int nlo, int ldl,
                                                               const int4* __restrict__ offs,
@@ -597,122 +728,19 @@ __global__ __launch_bounds__(64 * B) void sweep2d_band_kernel(int n1, int64_t n,
         const int first = band * B;
         const int lbase = first - Hy;   // line held in lb row 0
         if (L < n1) {
-            const int64_t rowbase = (int64_t)L * n1;
-            const int64_t mbase = REV ? (n - 1 - rowbase) : rowbase;
-            const T* Aline = A + rowbase * ldl;
-            int loff[MK];
-            bool lok[MK];
-#pragma unroll
-            for (int m = 0; m < MK; ++m) {
-                const int ly = L + ody[m];
-                lok[m] = oval[m] && ly >= 0 && ly < n1;
-                loff[m] = lok[m] ? (ly - lbase) * n1 + odx[m] : 0;
+            const bool stage = (w == 0) && (first > 0);
+            const bool last = (w == B - 1) || (L == n1 - 1);
+#define LGP_BAND_LINE(ST, LA)                                                                                \
+    band_line<T, MK, D, REV, SCALE, ST, LA>(n1, n, ldl, L, first, lbase, Hx, Hy, ody, odx, kcl, oval, A, scale, \
+                                            in, out, lb, w, zslot)
+            if (stage) {
+                if (last) LGP_BAND_LINE(true, true);
+                else LGP_BAND_LINE(true, false);
+            } else {
+                if (last) LGP_BAND_LINE(false, true);
+                else LGP_BAND_LINE(false, false);
             }
-            T a_s[D][MK];
-            T r_s[D];
-            auto issue = [&](int s, int ixp) {
-                ixp = min(ixp, n1 - 1);
-                const T* Ar = Aline + (int64_t)ixp * ldl;
-                const int64_t rm = REV ? (mbase - ixp) : (mbase + ixp);
-#pragma unroll
-                for (int m = 0; m < MK; ++m) a_s[s][m] = Ar[kcl[m]];
-                // vector loads (a relaxed atomic is never turned into a scalar
-                // load; scalar loads share lgkmcnt with LDS)
-                T rv = __hip_atomic_load(&in[rm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (SCALE) rv *= __hip_atomic_load(&scale[rm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                r_s[s] = rv;
-            };
-            const bool stager = (w == 0) && (first > 0) && (lane < Hy) && (lbase + lane >= 0);
-            const int sline = lbase + lane;
-            auto saddr = [&](int x) {
-                x = min(x, n1 - 1);
-                const int64_t rp = (int64_t)(stager ? sline : 0) * n1 + x;
-                return REV ? (n - 1 - rp) : rp;
-            };
-            T st_v[D];
-            // stage column x (value v loaded earlier; re-read while not ready)
-            auto stage_now = [&](int x, T v) {
-                const bool act = stager && x < n1;
-                if (__builtin_expect(__any(act && Sentinel<T>::is(v)), 0)) {
-                    int nap = 1;
-                    while (act && Sentinel<T>::is(v)) {
-                        backoff(nap);
-                        v = ld_coh(&out[saddr(x)]);
-                    }
-                }
-                if (act) lb[lane * n1 + x] = v;
-            };
-            if (w == 0 && first > 0) {
-                for (int x = 0; x < Hx && x < n1; ++x) stage_now(x, stager ? ld_coh(&out[saddr(x)]) : T(0));
-#pragma unroll
-                for (int s = 0; s < D; ++s) st_v[s] = stager ? ld_coh(&out[saddr(Hx + s)]) : T(0);
-            }
-            auto row = [&](int s, int ix) -> T {
-                if (w == 0 && first > 0) {
-                    const int x = ix + Hx;
-                    stage_now(x, st_v[s]);
-                    st_v[s] = stager ? ld_coh(&out[saddr(x + D)]) : T(0);
-                }
-                int idx[MK];
-#pragma unroll
-                for (int m = 0; m < MK; ++m) {
-                    const bool ok = lok[m] && (unsigned)(ix + odx[m]) < (unsigned)n1;
-                    idx[m] = ok ? loff[m] + ix : zslot;
-                }
-                T yv[MK];
-#pragma unroll
-                for (int m = 0; m < MK; ++m) yv[m] = lb[idx[m]];
-                bool miss = false;
-#pragma unroll
-                for (int m = 0; m < MK; ++m) miss |= Sentinel<T>::is(yv[m]);
-                if (__builtin_expect(__any(miss), 0)) {
-#pragma unroll
-                    for (int m = 0; m < MK; ++m) {
-                        while (Sentinel<T>::is(yv[m])) {
-                            __builtin_amdgcn_s_sleep(1);
-                            yv[m] = __hip_atomic_load(&lb[idx[m]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        }
-                    }
-                }
-                T acc = T(0);
-#pragma unroll
-                for (int m = 0; m < MK; ++m) acc += (idx[m] == zslot ? T(0) : a_s[s][m]) * yv[m];
-                return wave_sum_dpp(acc);
-            };
-            T* lbw = lb + (Hy + w) * n1;
-            const bool last_line = (w == B - 1) || (L == n1 - 1);
-            auto mrow = [&](int ixp) { return REV ? (mbase - ixp) : (mbase + ixp); };
-#pragma unroll
-            for (int s = 0; s < D; ++s) issue(s, s);
-            int ix0 = 0;
-            for (; ix0 + D <= n1; ix0 += D) {
-#pragma unroll
-                for (int s = 0; s < D; ++s) {
-                    const int ix = ix0 + s;
-                    const T acc = row(s, ix);
-                    const T y = Sentinel<T>::clean(r_s[s] - acc);
-                    issue(s, ix + D);
-                    if (lane == 0) {
-                        lbw[ix] = y;
-                        if (last_line) st_coh(&out[mrow(ix)], y);
-                    }
-                }
-                if (!last_line) {
-                    wait_lds();
-                    if (lane < D) st_coh(&out[mrow(ix0 + lane)], lbw[ix0 + lane]);
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < D; ++s) {
-                const int ix = ix0 + s;
-                if (ix < n1) {
-                    const T acc = row(s, ix);
-                    const T y = Sentinel<T>::clean(r_s[s] - acc);
-                    if (lane == 0) lbw[ix] = y;
-                }
-            }
-            wait_lds();
-            if (lane < n1 - ix0) st_coh(&out[mrow(ix0 + lane)], lbw[ix0 + lane]);
+#undef LGP_BAND_LINE
         }
         __syncthreads();
     }
@@ -772,6 +800,9 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
     const int bandT = n1 * W;
     const int nzW = (d == 3) ? W : 1;
     const int zoff = (int)(n * ldl);   // a row of zeros after the factor rows
+    // the ring is a whole number of PD-step chunks: npad no-op steps lead
+    const int nring = ((nsteps + PD - 1) / PD) * PD;
+    const int npad = nring - nsteps;
     // Control flow: the only lane-dependent branches sit in the middle of the
     // row loop; the loop head and tail are wave-uniform (scalar tickets and
     // pivots), so the compiler cannot turn a lane-0 block that straddles the
@@ -836,12 +867,18 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
         // Steps. Every step issues the same loads (a step whose row i+delta_j
         // leaves the grid, or a padding step past the end, reads the zero row
         // and leaves u_j = 0), so the load counter of each ring slot is static.
+        // ring of PD steps in flight: the gathered values, the pair word of
+        // each lane (~0u when the lane has no pair), the row offset of the step
         double g[PD][Q];
-        int kk[PD][Q], of[PD][Q];
+        unsigned pw[PD][Q];
         double dv[PD], mj[PD];
-        int jj[PD], rof[PD];
+        int jj[PD], rof[PD], rb[PD];
+        constexpr unsigned NOPAIR = 0xFFFFFFFFu;
+        auto kidx = [&](unsigned w2) { return w2 == NOPAIR ? nlo + 1 : (int)(w2 & 0xFFFFu); };
+        auto goff = [&](unsigned w2, int r0) { return w2 == NOPAIR ? zoff : r0 + (int)(w2 >> 16); };
         auto issue = [&](int b, int s) {
-            const bool live = s < nsteps;
+            s -= npad;   // the ring runs over npad no-op steps first
+            const bool live = s >= 0 && s < nsteps;
             const int sc = live ? s : 0;
             const int4 S = st_s[sc];
             const int dd = sd_s[sc];
@@ -855,21 +892,16 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
                                (unsigned)(iz + dz) < (unsigned)n1;
             jj[b] = live ? sj : nlo + 1;
             const int r0 = (i + slin) * ldl;
-            unsigned wd[Q];
+            rb[b] = r0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int p = pb + lane + 64 * q;
-                wd[q] = pw_s[(p < pe) ? p : 0];
-            }
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const bool act = valid && (pb + lane + 64 * q < pe);
-                kk[b][q] = act ? (int)(wd[q] & 0xFFFFu) : nlo + 1;
-                of[b][q] = act ? r0 + (int)(wd[q] >> 16) : zoff;
+                const unsigned wd = pw_s[(p < pe) ? p : 0];
+                pw[b][q] = (valid && p < pe) ? wd : NOPAIR;
             }
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                g[b][q] = __hip_atomic_load(LD + of[b][q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                g[b][q] = __hip_atomic_load(LD + goff(pw[b][q], r0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             rof[b] = valid ? r0 + nlo : zoff;
             dv[b] = __hip_atomic_load(LD + rof[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             mj[b] = u[jj[b]];   // M(i, i+delta_j) (0 when invalid); u_j is written only by step j
@@ -880,9 +912,7 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
 #pragma unroll
             for (int q = 0; q < Q; ++q) bad |= Sentinel<double>::is(g[b][q]);
             if (__builtin_expect(__any(bad), 0)) {
-                // the last steps of a row wait here for the rows one level
-                // back; poll at a fixed short interval (each coherent load is
-                // itself a round trip) so the row starts as soon as they land
+                // a step whose rows are not finished yet: poll its values
                 for (;;) {
                     bool still = false;
                     if (Sentinel<double>::is(dv[b])) {
@@ -892,7 +922,7 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
 #pragma unroll
                     for (int q = 0; q < Q; ++q)
                         if (Sentinel<double>::is(g[b][q])) {
-                            g[b][q] = ld_coh(LD + of[b][q]);
+                            g[b][q] = ld_coh(LD + goff(pw[b][q], rb[b]));
                             still |= Sentinel<double>::is(g[b][q]);
                         }
                     if (!__any(still)) break;
@@ -901,7 +931,7 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
             }
             double acc = 0.0;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) acc += u[kk[b][q]] * g[b][q];
+            for (int q = 0; q < Q; ++q) acc += u[kidx(pw[b][q])] * g[b][q];
             acc = wave_sum_dpp(acc);
             const double uj = mj[b] - acc;
             if (lane == 0) {
@@ -915,13 +945,37 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
         // next row, fetched while this row's first loads are in flight
         unsigned tkn = 0;
         if (lane == 0) tkn = atomicAdd(ticket, 1u);
-        for (int s0 = 0; s0 < nsteps; s0 += PD) {
+        for (int s0 = 0; s0 < nring - PD; s0 += PD) {
 #pragma unroll
             for (int b = 0; b < PD; ++b) {
                 consume(b);
                 issue(b, s0 + b + PD);
             }
         }
+        // The last PD steps wait for the rows one and two levels back, and
+        // their prefetched values are usually stale copies of the sentinel.
+        // Poll all of them together (one round trip per poll instead of one
+        // per step), then finish the row.
+        for (;;) {
+            bool still = false;
+#pragma unroll
+            for (int c = 0; c < PD; ++c) {
+                if (Sentinel<double>::is(dv[c])) {
+                    dv[c] = ld_coh(LD + rof[c]);
+                    still |= Sentinel<double>::is(dv[c]);
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+                    if (Sentinel<double>::is(g[c][q])) {
+                        g[c][q] = ld_coh(LD + goff(pw[c][q], rb[c]));
+                        still |= Sentinel<double>::is(g[c][q]);
+                    }
+            }
+            if (!__any(still)) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+#pragma unroll
+        for (int b = 0; b < PD; ++b) consume(b);
         // L(i, i+delta_k) = u_k / D(i+delta_k); D(i) = M(i,i) - sum_k u_k L(i, i+delta_k).
         // D(i) is the same in every lane; taking it from lane 0 makes the
         // pivot test and the stores below wave-uniform.
