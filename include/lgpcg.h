@@ -120,10 +120,10 @@ lgp_status lgp_ilu_backward(lgp_factor m, const double* y, double* z, void* stre
 /* Layout of a factor, for inspection. offsets (host, 3*noff ints, filled by
  * the library and valid while the handle lives) lists NZ(M) as (dx,dy,dz) in
  * column order; the first n_lower are the strictly lower ones. L (device)
- * is row-major with row stride ld >= n_lower + 1 (a multiple of 16, so rows
- * start on 128-byte boundaries): L[i*ld + k] = L(i, i + offset_k) for
- * k < n_lower, zero where the column leaves the grid, and L[i*ld + n_lower]
- * = 1/U(i,i). D (device, n) holds the pivots U(i,i). */
+ * is row-major with row stride ld >= n_lower + 1 (a multiple of 32, so rows
+ * start on 256-byte boundaries): L[i*ld + k] = L(i, i + offset_k) for
+ * k < n_lower, zero where the column leaves the grid, L[i*ld + n_lower]
+ * = 1/U(i,i), and zero after that. D (device, n) holds the pivots U(i,i). */
 typedef struct {
     int d, N, n1, Ta, Tb;
     int64_t n;

@@ -75,7 +75,7 @@ size_t plan_factor(Factor& F, void* buf, bool with32) {
     const int T = F.T, h = F.h, d = F.d, n1 = F.n1;
     int64_t tp = 1;
     for (int k = 0; k < d; ++k) tp *= (T + 1);
-    F.ldl = ((nlo + 1) + 15) & ~15;
+    F.ldl = ((nlo + 1) + 31) & ~31;
     const size_t ldl = (size_t)F.ldl;
     F.L = c.take<double>((size_t)(n + 1) * ldl);
     F.Ut = c.take<double>((size_t)n * ldl);
@@ -360,6 +360,15 @@ __global__ void level_order_kernel(int d, int n1, int64_t n, int A1, int B1, con
     }
 }
 
+// Row padding of the factor storage: entries [from, ldl) of every row are
+// set to zero (the substitution kernels read whole 32-entry groups).
+__global__ void zero_pad_kernel(int64_t rows, int ldl, int from, double* __restrict__ M) {
+    const int w = ldl - from;
+    const int64_t total = rows * w;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+        M[(e / w) * ldl + from + (e % w)] = 0.0;
+}
+
 // Backward-sweep operator in reversed row order: Ut[i'][k] = L(i - delta_k, i)
 // with i = n-1-i'. Tiled: a workgroup takes R consecutive output rows and
 // one run of offsets with equal (dy, dz) (consecutive k, dx ascending); the
@@ -601,6 +610,20 @@ __device__ inline void band_line(int n1, int64_t n, int ldl, int L, int first, i
         return REV ? (n - 1 - rp) : rp;
     };
     T st_v[D];
+    // The line just before the band is produced one level ahead of its use,
+    // so a value prefetched D rows earlier is always still the sentinel, and
+    // re-reading it serially would cost one device round trip per row. Every
+    // row therefore also issues one poll in which lanes Hy..63 read the next
+    // columns of that line; row x uses the lane of the poll issued KP rows
+    // earlier (already returned) that covers its column.
+    constexpr int KP = 4;
+    T pq[KP];
+    const int crit_lane = Hy + KP - 1;
+    auto paddr = [&](int x) {
+        const int xc = (lane >= Hy) ? x + Hx + 1 + (lane - Hy) : x;
+        const int64_t rp = (int64_t)(first - 1) * n1 + min(max(xc, 0), n1 - 1);
+        return REV ? (n - 1 - rp) : rp;
+    };
     // stage column x (value v loaded earlier; re-read while not ready)
     auto stage_now = [&](int x, T v) {
         const bool act = stager && x < n1;
@@ -616,12 +639,18 @@ __device__ inline void band_line(int n1, int64_t n, int ldl, int L, int first, i
         for (int x = 0; x < Hx && x < n1; ++x) stage_now(x, ld_coh(&out[saddr(x)]));
 #pragma unroll
         for (int s = 0; s < D; ++s) st_v[s] = ld_coh(&out[saddr(Hx + s)]);
+#pragma unroll
+        for (int r = 0; r < KP; ++r) pq[r] = ld_coh(&out[paddr(r - KP)]);
     }
     auto row = [&](int s, int ix) -> T {
         if (STAGE) {
             const int x = ix + Hx;
-            stage_now(x, st_v[s]);
+            T v = st_v[s];
+            const T vc = lane_val(pq[s % KP], crit_lane);   // column ix + Hx of line first-1
+            if (lane == Hy - 1 && !Sentinel<T>::is(vc)) v = vc;
+            stage_now(x, v);
             st_v[s] = ld_coh(&out[saddr(x + D)]);
+            pq[s % KP] = ld_coh(&out[paddr(ix)]);
         }
         int idx[MK];
 #pragma unroll
@@ -741,6 +770,240 @@ __global__ __launch_bounds__(64 * B) void sweep2d_band_kernel(int n1, int64_t n,
                 else LGP_BAND_LINE(false, false);
             }
 #undef LGP_BAND_LINE
+        }
+        __syncthreads();
+    }
+}
+
+// 2D substitution, two grid lines per wave. A workgroup owns a band of
+// B = 2*NW consecutive lines; wave v walks lines first+2v (lanes 0..31) and
+// first+2v+1 (lanes 32..63), the second trailing the first by Hx+1 columns
+// so that every value it needs from the first line was produced by the same
+// wave one step earlier. Each half-wave holds SL offsets per lane (k = j +
+// 32m), so the reduction, the readiness test, the stores and the staging are
+// paid once per two rows. Line buffers in LDS carry Hx zero columns on either
+// side and lines outside the grid are all zero, so no offset needs a mask;
+// entries past n_lower in the factor rows are zero or finite and meet a zero
+// LDS slot. A row is ready when its dot product is not NaN (the sentinel is
+// a NaN): one test per step, and the slow path re-reads only while a
+// sentinel is seen. Every path through a step issues the same loads and
+// stores (idle half-waves store the value already in LDS).
+__device__ inline double dpp_bcast15(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x142, 0xA, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x142, 0xA, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float dpp_bcast15(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+}
+
+template <typename T, int SL, int D, int NW, bool REV, bool SCALE, bool STAGE>
+__device__ inline void pair_walk(int n1, int64_t n, int ldl, int first, int lbase, int Hx, int Hy, int Wd,
+                                 int zslot, const int (&boff)[SL], const int (&bstep)[SL],
+                                 const T* __restrict__ A, const T* __restrict__ scale,
+                                 const T* __restrict__ in, T* __restrict__ out, T* lb, int wv) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 5, j = lane & 31;
+    const int A1 = Hx + 1;
+    // line within the band; a half-wave whose line lies beyond the grid
+    // repeats the wave's first line (same values to the same addresses)
+    const int li = (first + 2 * wv + g < n1) ? 2 * wv + g : 2 * wv;
+    const int L = first + li;
+    const bool lin = true;
+    const int Lc = L;
+    const int skew = li * A1;
+    const int t0 = 2 * wv * A1;                                  // first step with work
+    const int tend = min(n1 - 1 + (2 * wv + 1) * A1, n1 - 1 + (2 * NW - 1) * A1);
+    const int own = (L - lbase) * Wd + Hx;                       // LDS index of column 0 of this line
+    auto xcl = [&](int t) { return min(max(t - skew, 0), n1 - 1); };
+    auto mrow = [&](int x) {
+        const int64_t rp = (int64_t)Lc * n1 + x;
+        return REV ? (n - 1 - rp) : rp;
+    };
+    // ring of D steps in flight: the factor row (SL entries per lane), then
+    // the right-hand side of the row and, for the backward sweep, its scale
+    // (multiplied at use, so the loads are not waited for when issued)
+    T a_s[D][SL + 2];
+    auto issue = [&](int s, int t) {
+        const int x = xcl(t);
+        const T* Ar = A + ((int64_t)Lc * n1 + x) * ldl + j;
+#pragma unroll
+        for (int m = 0; m < SL; ++m) a_s[s][m] = Ar[32 * m];
+        // the two half-waves read different rows, so these stay vector loads
+        const int64_t rm = mrow(x);
+        a_s[s][SL] = in[rm];
+        if (SCALE) a_s[s][SL + 1] = scale[rm];
+    };
+    // staging of the Hy lines before the band (wave 0 of every band but the
+    // first): lane l < Hy stages line lbase + l; the line just before the band
+    // is polled in flight as well (see below)
+    constexpr int KP = 4;
+    const bool stager = STAGE && (lane < Hy) && (lbase + lane >= 0);
+    const int sline = stager ? lbase + lane : 0;
+    const int crit_lane = Hy + KP - 1;
+    auto saddr = [&](int c) {
+        const int64_t rp = (int64_t)sline * n1 + min(c, n1 - 1);
+        return REV ? (n - 1 - rp) : rp;
+    };
+    auto paddr = [&](int c) {
+        const int cc = (lane >= Hy) ? c + 1 + (lane - Hy) : c;
+        const int64_t rp = (int64_t)(first - 1) * n1 + min(max(cc, 0), n1 - 1);
+        return REV ? (n - 1 - rp) : rp;
+    };
+    T st_v[D], pq[KP];
+    auto stage_now = [&](int c, T v) {
+        const bool act = stager && c < n1;
+        if (__builtin_expect(__any(act && Sentinel<T>::is(v)), 0)) {
+            while (act && Sentinel<T>::is(v)) {
+                __builtin_amdgcn_s_sleep(1);
+                v = ld_coh(&out[saddr(c)]);
+            }
+        }
+        if (act) lb[lane * Wd + Hx + c] = v;
+    };
+    if (STAGE) {
+        for (int c = 0; c < Hx && c < n1; ++c) stage_now(c, ld_coh(&out[saddr(c)]));
+#pragma unroll
+        for (int s = 0; s < D; ++s) st_v[s] = ld_coh(&out[saddr(Hx + s)]);
+#pragma unroll
+        for (int r = 0; r < KP; ++r) pq[r] = ld_coh(&out[paddr(Hx + r - KP)]);
+    }
+    auto step = [&](int s, int t) {
+        if (STAGE) {
+            // wave 0's first line is at column t and needs column t + Hx of
+            // the staged lines; the poll issued KP steps ago covers it
+            const int c = t + Hx;
+            T v = st_v[s];
+            const T vc = lane_val(pq[s % KP], crit_lane);
+            if (lane == Hy - 1 && !Sentinel<T>::is(vc)) v = vc;
+            stage_now(c, v);
+            st_v[s] = ld_coh(&out[saddr(c + D)]);
+            pq[s % KP] = ld_coh(&out[paddr(c)]);
+        }
+        const int xr = t - skew;
+        const bool act = lin && xr >= 0 && xr < n1;
+        const int x = min(max(xr, 0), n1 - 1);
+        const T prev = lb[own + x];   // what LDS holds for this row (stored by idle half-waves)
+        T yv[SL];
+#pragma unroll
+        for (int m = 0; m < SL; ++m) yv[m] = lb[boff[m] + x * bstep[m]];
+        T acc0 = T(0), acc1 = T(0);
+#pragma unroll
+        for (int m = 0; m < SL; m += 2) acc0 += a_s[s][m] * yv[m];
+#pragma unroll
+        for (int m = 1; m < SL; m += 2) acc1 += a_s[s][m] * yv[m];
+        T acc = act ? acc0 + acc1 : T(0);
+        if (__builtin_expect(__any(acc != acc), 0)) {
+            // some operand is not written yet (or a genuine NaN): wait for
+            // the sentinels to go, then recompute
+            for (;;) {
+                bool still = false;
+#pragma unroll
+                for (int m = 0; m < SL; ++m)
+                    if (Sentinel<T>::is(yv[m])) {
+                        yv[m] = __hip_atomic_load(&lb[boff[m] + x * bstep[m]], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+                        still |= Sentinel<T>::is(yv[m]);
+                    }
+                if (!__any(act && still)) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            acc0 = T(0);
+            acc1 = T(0);
+#pragma unroll
+            for (int m = 0; m < SL; m += 2) acc0 += a_s[s][m] * yv[m];
+#pragma unroll
+            for (int m = 1; m < SL; m += 2) acc1 += a_s[s][m] * yv[m];
+            acc = act ? acc0 + acc1 : T(0);
+        }
+        // half-wave sums: rows of 16 lanes, then row 0 into row 1 and row 2
+        // into row 3; lanes 16..31 and 48..63 hold the two totals
+        acc += dpp_v<0xB1>(acc);
+        acc += dpp_v<0x4E>(acc);
+        acc += dpp_v<0x141>(acc);
+        acc += dpp_v<0x140>(acc);
+        acc += dpp_bcast15(acc);
+        const T tot = g ? lane_val(acc, 63) : lane_val(acc, 31);
+        const T rr = SCALE ? a_s[s][SL] * a_s[s][SL + 1] : a_s[s][SL];
+        const T y = Sentinel<T>::clean(rr - tot);
+        // the new loads of this ring slot must not move above the last use
+        // of its old values, or the ring needs one register more and the
+        // compiler rotates it with copies that wait for the newest loads
+        asm volatile("" ::"v"(y) : "memory");
+        issue(s, t + D);
+        if (act && (lane == 31 || lane == 63)) lb[own + x] = y;
+        // every lane stores (the same value within a half-wave); an idle
+        // half-wave stores what LDS already holds for its clamped row, which
+        // only it writes, so this never replaces a result
+        st_coh(&out[mrow(x)], act ? y : prev);
+    };
+#pragma unroll
+    for (int s = 0; s < D; ++s) issue(s, t0 + s);
+    int t = t0;
+    for (; t + D - 1 <= tend; t += D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) step(s, t + s);
+    }
+#pragma unroll
+    for (int s = 0; s < D; ++s)
+        if (t + s <= tend) step(s, t + s);
+}
+
+template <typename T, int SL, int D, int NW, bool REV, bool SCALE>
+__global__ __launch_bounds__(64 * NW) void sweep2d_pair_kernel(int n1, int64_t n, int nlo, int ldl,
+                                                               const int4* __restrict__ offs, const T* __restrict__ A,
+                                                               const T* __restrict__ scale, const T* __restrict__ in,
+                                                               T* __restrict__ out, unsigned* ticket,
+                                                               const int* __restrict__ stop, int Hx, int Hy) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T* lb = (T*)smem_raw;   // [Hy + B][n1 + 2 Hx] line buffers, then one zero slot
+    __shared__ int s_band;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (stop && *stop) return;
+    constexpr int B = 2 * NW;
+    const int nbands = (n1 + B - 1) / B;
+    const int Wd = n1 + 2 * Hx;
+    const int nl = Hy + B;
+    const int zslot = nl * Wd;
+    const int g = lane >> 5, j = lane & 31;
+    for (;;) {
+        if (tid == 0) {
+            const unsigned tk = atomicAdd(ticket, 1u);
+            s_band = (tk < (unsigned)nbands) ? (int)tk : -1;
+        }
+        __syncthreads();
+        const int band = __builtin_amdgcn_readfirstlane(s_band);
+        if (band < 0) break;
+        const int first = band * B;
+        const int lbase = first - Hy;
+        // lines above the grid and the Hx columns either side are zero; the
+        // rest waits for its values
+        for (int e = tid; e < nl * Wd; e += 64 * NW) {
+            const int r = e / Wd, c = e - r * Wd;
+            const bool zero = (lbase + r < 0) || c < Hx || c >= Hx + n1;
+            lb[e] = zero ? T(0) : Sentinel<T>::value();
+        }
+        if (tid == 0) lb[zslot] = T(0);
+        __syncthreads();
+        if (first + 2 * wv < n1) {
+            const int L = (first + 2 * wv + g < n1) ? first + 2 * wv + g : first + 2 * wv;
+            int boff[SL], bstep[SL];
+#pragma unroll
+            for (int m = 0; m < SL; ++m) {
+                const int k = j + 32 * m;
+                const bool ok = k < nlo;
+                const int4 o = offs[ok ? k : 0];
+                boff[m] = ok ? (L + o.y - lbase) * Wd + Hx + o.x : zslot;
+                bstep[m] = ok ? 1 : 0;
+            }
+            if (wv == 0 && first > 0)
+                pair_walk<T, SL, D, NW, REV, SCALE, true>(n1, n, ldl, first, lbase, Hx, Hy, Wd, zslot, boff, bstep,
+                                                          A, scale, in, out, lb, wv);
+            else
+                pair_walk<T, SL, D, NW, REV, SCALE, false>(n1, n, ldl, first, lbase, Hx, Hy, Wd, zslot, boff,
+                                                           bstep, A, scale, in, out, lb, wv);
         }
         __syncthreads();
     }
@@ -1249,6 +1512,11 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
                            (const int4*)F.d_offs, (const double*)F.L, F.Ut);
     }
     LGP_CHECK_LAUNCH();
+    // after 1/D at n_lower, rows of L and Ut end in zeros
+    if (F.ldl > F.nlo + 1)
+        hipLaunchKernelGGL(zero_pad_kernel, dim3(4096), dim3(256), 0, s, n, F.ldl, F.nlo + 1, F.L);
+    hipLaunchKernelGGL(zero_pad_kernel, dim3(4096), dim3(256), 0, s, n, F.ldl, F.nlo, F.Ut);
+    LGP_CHECK_LAUNCH();
     if (F.has32) {
         hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.ldl, (const double*)F.L, F.L32);
         hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.ldl, (const double*)F.Ut, F.Ut32);
@@ -1269,8 +1537,31 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
     LGP_CHECK_LAUNCH();
     const int64_t n = F.n;
     constexpr int BB = 8, DD = 8;
+    // two lines per wave, NW = 4 waves: bands of 8 lines
+    constexpr int PNW = 4;
+    const size_t pair_shmem = ((size_t)(2 * PNW + F.Hy) * (F.n1 + 2 * F.Hx) + 1) * sizeof(T);
+    const int SLn = (F.nlo + 31) / 32;
     const size_t band_shmem = ((size_t)(BB + F.Hy) * F.n1 + 1) * sizeof(T);
-    if (F.d == 2 && F.nlo <= 8 * 64 && band_shmem <= 150 * 1024) {
+    if (F.d == 2 && SLn >= 1 && SLn <= 8 && 32 * SLn <= F.ldl && F.Hy + 4 <= 64 && pair_shmem <= 150 * 1024) {
+        const int nbands = (F.n1 + 2 * PNW - 1) / (2 * PNW);
+        hipLaunchKernelGGL(fill_sentinel_kernel<T>, dim3(std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, s,
+                           n, out, stop);
+        auto pick = [&](auto kf) {
+            hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pair_shmem);
+            const int grid = persistent_grid((const void*)kf, 64 * PNW, pair_shmem, nbands);
+            hipLaunchKernelGGL(kf, dim3(grid), dim3(64 * PNW), pair_shmem, s, F.n1, n, F.nlo, F.ldl,
+                               (const int4*)F.d_offs, A, scale, in, out, tick, stop, F.Hx, F.Hy);
+        };
+#define LGP_PAIR(SLv)                                                                    \
+    case SLv:                                                                            \
+        if (backward) pick(sweep2d_pair_kernel<T, SLv, DD, PNW, true, true>);            \
+        else pick(sweep2d_pair_kernel<T, SLv, DD, PNW, false, false>);                   \
+        break;
+        switch (SLn) {
+            LGP_PAIR(1) LGP_PAIR(2) LGP_PAIR(3) LGP_PAIR(4) LGP_PAIR(5) LGP_PAIR(6) LGP_PAIR(7) LGP_PAIR(8)
+        }
+#undef LGP_PAIR
+    } else if (F.d == 2 && F.nlo <= 8 * 64 && band_shmem <= 150 * 1024) {
         const int nbands = (F.n1 + BB - 1) / BB;
         hipLaunchKernelGGL(fill_sentinel_kernel<T>, dim3(std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, s,
                            n, out, stop);

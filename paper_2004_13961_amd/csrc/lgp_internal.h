@@ -93,7 +93,7 @@ struct Factor {
     int d, n1, Ta, Tb, T, h;   // h = reach of the pattern per direction
     int64_t n;
     int noff, nlo;             // pattern size, number of strictly lower offsets
-    int ldl;                   // row stride of L / Ut (>= nlo + 1, multiple of 16 doubles)
+    int ldl;                   // row stride of L / Ut (>= nlo + 1, multiple of 32 doubles)
     std::vector<int> offs;     // host, 3*noff
     int Hx, Hy, Hz;            // max |offset| per direction
     int nlines;                // lines of constant (y,z)
