@@ -99,6 +99,29 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = {"factor": "paper_2004_13961_amd/csrc/ilu.hip", "sweep": "paper_2004_13961_amd/csrc/ilu.hip",
+                  "matvec": "paper_2004_13961_amd/csrc/gemm.hip"}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter figures
+    (profiles/traffic_<kernel>_<workload>.json: FETCH_SIZE and WRITE_SIZE per
+    dispatch, scaled by what the same counters read for a copy of known
+    size). None when there are none or the kernel's source file changed since
+    they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    with open(os.path.join(ROOT, KERNEL_SOURCES[kernel]), "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    if rec.get("source_sha256") != digest:
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +131,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=100000)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="finish with one device-to-device copy of this many bytes (a reference "
+                         "for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this solver runs each request on a single GPU "
@@ -184,6 +210,12 @@ def main():
     for _ in range(nsw):
         M.forward(u, y)
     ev[3].record()
+    for _ in range(2):
+        M.backward(u, y)
+    ev[4].record()
+    for _ in range(nsw):
+        M.backward(u, y)
+    ev[5].record()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     M_t = Factor(P, T)
@@ -191,28 +223,42 @@ def main():
     t_factor = time.perf_counter() - t0
     mv_ms = ev[0].elapsed_time(ev[1]) / nmv
     sw_ms = ev[2].elapsed_time(ev[3]) / nsw
+    swb_ms = ev[4].elapsed_time(ev[5]) / nsw
     mv_tflops = matvec_flops(d, N) / (mv_ms * 1e-3) / 1e12
     desc = M.describe()
+    fac_ms = float(M_t.describe()["factor_kernel_ms"])   # ILU(0) kernel, HIP events on the library's stream
     nnz = nnz_lower(d, N - 1, desc["offsets"])
     n = P.n
     sweep_bytes = nnz * 8 + 2 * n * 8      # L entries in the grid, r read, y written
     sw_gbs = sweep_bytes / (sw_ms * 1e-3) / 1e9
+    # ILU(0): every in-grid entry of L and every pivot written once, and each
+    # row of L read at least once by the rows that use it
+    factor_bytes = 2 * (nnz + n) * 8
 
     iters = info_s["iters"]
-    t_sweeps = 2 * iters * sw_ms
-    t_mv = (iters + 2) * mv_ms
-    if t_sweeps >= t_mv:
-        roof = dict(kernel="sweep_kernel (ILU forward/backward substitution)", bound="hbm",
+    # time of each candidate kernel inside one step
+    share = {"factor": fac_ms, "sweep": iters * (sw_ms + swb_ms), "matvec": (iters + 2) * mv_ms}
+    dominant = max(share, key=share.get)
+    if dominant == "factor":
+        ach = factor_bytes / (fac_ms * 1e-3) / 1e9
+        roof = dict(kernel="ilu_factor2_kernel (ILU(0), Alg. 2)", bound="hbm", achieved=round(ach, 2),
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 6),
+                    bytes_per_launch=factor_bytes, launch_ms=round(fac_ms, 3))
+    elif dominant == "sweep":
+        roof = dict(kernel="sweep2d_pair_kernel (forward substitution, Alg. 3)", bound="hbm",
                     achieved=round(sw_gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(sw_gbs / HBM_PEAK_GBS, 5), traffic=None,
-                    bytes_per_launch=sweep_bytes, launch_ms=round(sw_ms, 4))
+                    frac=round(sw_gbs / HBM_PEAK_GBS, 5), bytes_per_launch=sweep_bytes,
+                    launch_ms=round(sw_ms, 4))
     else:
         roof = dict(kernel="gemm_k4_kernel<double> (sum-factorised matvec)", bound="mfma",
                     achieved=round(mv_tflops, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(mv_tflops / FP64_PEAK_TFLOPS, 5), traffic=None,
-                    flops_per_matvec=matvec_flops(d, N), launch_ms=round(mv_ms, 4))
+                    frac=round(mv_tflops / FP64_PEAK_TFLOPS, 5), flops_per_matvec=matvec_flops(d, N),
+                    launch_ms=round(mv_ms, 4))
+    roof["traffic"] = measured_traffic(dominant, cfg.name)
+    roof["time_share_ms"] = {k: round(v, 3) for k, v in share.items()}
 
-    log("matvec %.4f ms, sweep %.4f ms, factor %.1f ms" % (mv_ms, sw_ms, t_factor * 1e3))
+    log("matvec %.4f ms, sweeps %.4f / %.4f ms, factor %.1f ms (kernel %.1f ms)" % (mv_ms, sw_ms, swb_ms,
+                                                                                   t_factor * 1e3, fac_ms))
     mixed = {}
     if not args.no_mixed:
         xd = x.clone()
@@ -257,6 +303,8 @@ def main():
         "matvec_tflops": round(mv_tflops, 3),
         "matvec_frac_fp64_peak": round(mv_tflops / FP64_PEAK_TFLOPS, 4),
         "sweep_ms": round(sw_ms, 4),
+        "sweep_backward_ms": round(swb_ms, 4),
+        "factor_kernel_ms": round(fac_ms, 3),
         "sweep_gbs": round(sw_gbs, 2),
         "sweep_levels": desc["levels"],
         "mixed": mixed,
@@ -271,6 +319,13 @@ def main():
                                "kind": "oracle",
                                "sample": cb["sample"] + "; total scaled to the GPU's %d iterations" % iters}
     print(json.dumps(out))
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes" % (src.numel() * 8))
 
 
 if __name__ == "__main__":

@@ -133,6 +133,8 @@ typedef struct {
     const double* D;
     int levels;          /* hyperplane depth of the sweeps */
     int ld;              /* row stride of L in doubles */
+    double factor_kernel_ms; /* duration of the ILU(0) kernel of this factorisation,
+                                from HIP events on the caller's stream (-1 if unknown) */
 } lgp_factor_desc;
 lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out);
 

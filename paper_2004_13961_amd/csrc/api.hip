@@ -359,6 +359,7 @@ lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out) {
     out->D = F.Dg;
     out->levels = F.levels;
     out->ld = F.ldl;
+    out->factor_kernel_ms = F.factor_kernel_ms;
     return LGP_OK;
 }
 

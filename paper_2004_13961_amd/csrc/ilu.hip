@@ -1276,17 +1276,26 @@ struct FactorHostTables {
     std::vector<unsigned> pw;
 };
 
-static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& H);
+static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& H, hipEvent_t* ev);
 
 lgp_status factor_build(Factor& F, hipStream_t s) {
     FactorHostTables H;
-    lgp_status st = factor_build_impl(F, s, H);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const bool timed = hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
+    F.factor_kernel_ms = -1.0f;
+    lgp_status st = factor_build_impl(F, s, H, timed ? ev : nullptr);
     // drain the stream before H goes away, on success and on failure alike
     if (hipStreamSynchronize(s) != hipSuccess && st == LGP_OK) st = LGP_E_HIP;
+    if (timed && st == LGP_OK) {
+        float ms = -1.0f;
+        if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) F.factor_kernel_ms = ms;
+    }
+    for (auto& e : ev)
+        if (e) hipEventDestroy(e);
     return st;
 }
 
-static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& H) {
+static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& H, hipEvent_t* ev) {
     const int d = F.d, n1 = F.n1, T = F.T, h = F.h;
     const int W = 2 * h + 1, T1 = T + 1;
     const int64_t n = F.n;
@@ -1469,22 +1478,26 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
         const size_t shmem = tab_bytes + wpb * wave_bytes;
         hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         const int grid = persistent_grid((const void*)kf, 64 * wpb, shmem, (n + wpb - 1) / wpb);
+        if (ev) hipEventRecord(ev[0], s);
         hipLaunchKernelGGL(kf, dim3(grid), dim3(64 * wpb), shmem, s, d, n1, n, F.nlo, F.ldl, F.nlo, F.npairs, T, h,
                            (const int4*)F.d_offs, (const int4*)F.steps, (const int*)F.sdxyz,
                            (const unsigned*)F.pairw, (const int*)d_order, (const double*)F.band,
                            (const double*)fold, F.L, F.Dg, F.invD, F.ticket, F.flag);
         LGP_CHECK_LAUNCH();
+        if (ev) hipEventRecord(ev[1], s);
     } else {
         // done flags live in the y_tmp buffer (n doubles >= n unsigned)
         unsigned* done = (unsigned*)F.y_tmp;
         LGP_HIP(hipMemsetAsync(done, 0, (size_t)n * 4, s));
         const size_t shmem = (size_t)(F.nlo + 1) * 8;
         const int grid = persistent_grid((const void*)ilu_factor_kernel, 64, shmem, n);
+        if (ev) hipEventRecord(ev[0], s);
         hipLaunchKernelGGL(ilu_factor_kernel, dim3(grid), dim3(64), shmem, s, d, n1, n, F.nlo, F.ldl, T, h,
                            (const int4*)F.d_offs, (const int*)d_order, (const double*)F.band, (const double*)fold,
                            (const int*)F.pair_ptr, (const int*)F.pair_j, (const int*)F.pair_l, F.L, F.Dg,
                            F.invD, done, F.ticket, F.flag);
         LGP_CHECK_LAUNCH();
+        if (ev) hipEventRecord(ev[1], s);
     }
     // runs of lower offsets with equal (dy, dz)
     std::vector<int>& runs = H.runs;

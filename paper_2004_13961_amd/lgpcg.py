@@ -43,7 +43,8 @@ class FactorDesc(ctypes.Structure):
                 ("Ta", ctypes.c_int), ("Tb", ctypes.c_int), ("n", ctypes.c_int64),
                 ("noff", ctypes.c_int), ("n_lower", ctypes.c_int),
                 ("offsets", ctypes.POINTER(ctypes.c_int)), ("L", ctypes.c_void_p),
-                ("D", ctypes.c_void_p), ("levels", ctypes.c_int), ("ld", ctypes.c_int)]
+                ("D", ctypes.c_void_p), ("levels", ctypes.c_int), ("ld", ctypes.c_int),
+                ("factor_kernel_ms", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):
