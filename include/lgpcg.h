@@ -135,6 +135,11 @@ typedef struct {
     int ld;              /* row stride of L in doubles */
     double factor_kernel_ms; /* duration of the ILU(0) kernel of this factorisation,
                                 from HIP events on the caller's stream (-1 if unknown) */
+    int factor_kernel;   /* which ILU(0) kernel built it: 2 = dataflow kernel (one row per
+                            wavefront, pair tables in LDS), 1 = generic level-ordered kernel.
+                            The environment variable LGP_FACTOR_KERNEL=1|2 restricts the
+                            choice to that kernel where it applies (else the generic one
+                            runs); unset or 0 takes 2 where it applies. */
 } lgp_factor_desc;
 lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out);
 

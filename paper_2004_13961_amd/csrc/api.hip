@@ -360,6 +360,7 @@ lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out) {
     out->levels = F.levels;
     out->ld = F.ldl;
     out->factor_kernel_ms = F.factor_kernel_ms;
+    out->factor_kernel = F.factor_kernel;
     return LGP_OK;
 }
 

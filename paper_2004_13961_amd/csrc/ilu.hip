@@ -24,6 +24,7 @@
 //     iz-1), which by induction covers every other dependency.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "lgp_internal.h"
 
@@ -1169,26 +1170,28 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
             dv[b] = __hip_atomic_load(LD + rof[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             mj[b] = u[jj[b]];   // M(i, i+delta_j) (0 when invalid); u_j is written only by step j
         };
+        // A poll re-reads the values of a slot that are still sentinels (in
+        // place, in the lanes that hold them), all before the first check:
+        // one round trip however many values it waits for.
+        auto reload = [&](int c) {
+            if (Sentinel<double>::is(dv[c])) dv[c] = ld_coh(LD + rof[c]);
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (Sentinel<double>::is(g[c][q])) g[c][q] = ld_coh(LD + goff(pw[c][q], rb[c]));
+        };
+        auto pending = [&](int c) {
+            bool bad = Sentinel<double>::is(dv[c]);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) bad |= Sentinel<double>::is(g[c][q]);
+            return bad;
+        };
         double piv = 0.0;
         auto consume = [&](int b) {
-            bool bad = Sentinel<double>::is(dv[b]);
-#pragma unroll
-            for (int q = 0; q < Q; ++q) bad |= Sentinel<double>::is(g[b][q]);
-            if (__builtin_expect(__any(bad), 0)) {
+            if (__builtin_expect(__any(pending(b)), 0)) {
                 // a step whose rows are not finished yet: poll its values
                 for (;;) {
-                    bool still = false;
-                    if (Sentinel<double>::is(dv[b])) {
-                        dv[b] = ld_coh(LD + rof[b]);
-                        still |= Sentinel<double>::is(dv[b]);
-                    }
-#pragma unroll
-                    for (int q = 0; q < Q; ++q)
-                        if (Sentinel<double>::is(g[b][q])) {
-                            g[b][q] = ld_coh(LD + goff(pw[b][q], rb[b]));
-                            still |= Sentinel<double>::is(g[b][q]);
-                        }
-                    if (!__any(still)) break;
+                    reload(b);
+                    if (!__any(pending(b))) break;
                     __builtin_amdgcn_s_sleep(1);
                 }
             }
@@ -1215,26 +1218,39 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
                 issue(b, s0 + b + PD);
             }
         }
-        // The last PD steps wait for the rows one and two levels back, and
-        // their prefetched values are usually stale copies of the sentinel.
-        // Poll all of them together (one round trip per poll instead of one
-        // per step), then finish the row.
+        // The last PD steps wait for the rows one and two levels back: the
+        // hyperplane chain runs through them, so from here on the wave runs
+        // at raised priority. The entries of the other steps are final:
+        // publish them first, then poll the late steps together (one round trip per poll instead of one per
+        // step), finish them and publish their entries, 1/D and D. Every
+        // store instruction runs in all lanes (the counters stay static):
+        // a lane without an entry of its own repeats the store of another
+        // lane (same address, same value) -- never a shared location, which
+        // would turn into one hot line for the whole chip.
+        __builtin_amdgcn_s_setprio(3);
+        double* Li = LD + (int64_t)i * ldl;
+        if (nsteps > PD) {   // wave-uniform; false only for tiny stencils
+            const int k0 = __builtin_amdgcn_readfirstlane(st_s[0].x);   // first step: never a late one
+#pragma unroll
+            for (int m = 0; m < Q; ++m) {
+                const int k = lane + 64 * m;
+                bool own = k < nlo;
+#pragma unroll
+                for (int b = 0; b < PD; ++b) own &= (k != jj[b]);
+                const int kk = own ? k : k0;
+                st_coh(Li + kk, Sentinel<double>::clean(u[kk] * w[kk]));
+            }
+        }
         for (;;) {
             bool still = false;
 #pragma unroll
-            for (int c = 0; c < PD; ++c) {
-                if (Sentinel<double>::is(dv[c])) {
-                    dv[c] = ld_coh(LD + rof[c]);
-                    still |= Sentinel<double>::is(dv[c]);
+            for (int c = 0; c < PD; ++c)
+                if (__any(pending(c))) {   // wave-uniform
+                    reload(c);
+                    still = true;
                 }
-#pragma unroll
-                for (int q = 0; q < Q; ++q)
-                    if (Sentinel<double>::is(g[c][q])) {
-                        g[c][q] = ld_coh(LD + goff(pw[c][q], rb[c]));
-                        still |= Sentinel<double>::is(g[c][q]);
-                    }
-            }
-            if (!__any(still)) break;
+            if (!still) break;
+            // one wait for all re-reads, at the next check
             __builtin_amdgcn_s_sleep(1);
         }
 #pragma unroll
@@ -1246,11 +1262,20 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
         const double Dii = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(Dr)),
                                             __builtin_amdgcn_readfirstlane(__double2loint(Dr)));
         const double iv = 1.0 / Dii;
-        double* Li = LD + (int64_t)i * ldl;
-        for (int k = lane; k <= nlo; k += 64)
-            st_coh(Li + k, Sentinel<double>::clean(k < nlo ? u[k] * w[k] : iv));
+        if (nsteps > PD) {
+            // lanes 0..PD-1: the late steps' entries; the other lanes (and
+            // padding steps) store 1/D
+            int kl = nlo;
+#pragma unroll
+            for (int b = 0; b < PD; ++b) kl = (lane == b && jj[b] < nlo) ? jj[b] : kl;
+            st_coh(Li + kl, Sentinel<double>::clean(kl < nlo ? u[kl] * w[kl] : iv));
+        } else {
+            for (int k = lane; k <= nlo; k += 64)
+                st_coh(Li + k, Sentinel<double>::clean(k < nlo ? u[k] * w[k] : iv));
+        }
         Dg[i] = Dii;    // the same value from every lane
         invD[i] = iv;
+        __builtin_amdgcn_s_setprio(0);
         if (!(Dii > 0.0) || !isfinite(Dii)) atomicOr(flag, 1);   // uniform branch; one atomic per lane, rare
         tk = __builtin_amdgcn_readfirstlane(tkn);
     }
@@ -1467,10 +1492,16 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
     const size_t wave_bytes = (size_t)(2 * F.nlo + 4) * 8;
     int wpb = 16;
     while (wpb > 4 && tab_bytes + wpb * wave_bytes > 150 * 1024) wpb /= 2;
+    // LGP_FACTOR_KERNEL = 1 or 2 restricts the choice to that kernel where it
+    // applies (for tests of both); 0 or unset takes the dataflow kernel (2)
+    // where it applies, else the generic one (1)
+    const char* kenv = std::getenv("LGP_FACTOR_KERNEL");
+    const int kpick = kenv ? std::atoi(kenv) : 0;
     const bool dataflow = F.maxpairs <= 64 * FQ && F.nlo + 1 <= 64 * FQ &&
                           (int64_t)(n + 1) * F.ldl < (int64_t)INT32_MAX &&
-                          tab_bytes + wpb * wave_bytes <= 150 * 1024;
+                          tab_bytes + wpb * wave_bytes <= 150 * 1024 && (kpick == 0 || kpick == 2);
     if (dataflow) {
+        F.factor_kernel = 2;
         hipLaunchKernelGGL(fill_sentinel_kernel<double>, dim3(std::min<int64_t>(8192, (n * F.ldl + 255) / 256)),
                            dim3(256), 0, s, (int64_t)n * F.ldl, F.L, (const int*)nullptr);
         LGP_CHECK_LAUNCH();
@@ -1486,6 +1517,7 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
         LGP_CHECK_LAUNCH();
         if (ev) hipEventRecord(ev[1], s);
     } else {
+        F.factor_kernel = 1;
         // done flags live in the y_tmp buffer (n doubles >= n unsigned)
         unsigned* done = (unsigned*)F.y_tmp;
         LGP_HIP(hipMemsetAsync(done, 0, (size_t)n * 4, s));

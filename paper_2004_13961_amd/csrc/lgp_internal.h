@@ -125,6 +125,7 @@ struct Factor {
     int* runs;        // [nruns][4] runs of lower offsets with equal (dy, dz): {kb, ke, dx_first, dx_last}
     int nruns;
     float factor_kernel_ms;   // duration of the ILU(0) kernel of the last build (HIP events)
+    int factor_kernel;        // 2: dataflow kernel, 1: generic kernel
     double* y_tmp;    // [n] intermediate of precond_apply
     bool has32;
     size_t bytes;

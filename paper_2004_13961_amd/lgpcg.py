@@ -44,7 +44,7 @@ class FactorDesc(ctypes.Structure):
                 ("noff", ctypes.c_int), ("n_lower", ctypes.c_int),
                 ("offsets", ctypes.POINTER(ctypes.c_int)), ("L", ctypes.c_void_p),
                 ("D", ctypes.c_void_p), ("levels", ctypes.c_int), ("ld", ctypes.c_int),
-                ("factor_kernel_ms", ctypes.c_double)]
+                ("factor_kernel_ms", ctypes.c_double), ("factor_kernel", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):

@@ -125,7 +125,8 @@ class Factor:
         rows = self.buf[dsc.L - base: dsc.L - base + n * ld * 8].view(torch.float64).view(n, ld)
         Dv = self.buf[dsc.D - base: dsc.D - base + n * 8].view(torch.float64)
         return dict(offsets=offs, n_lower=nlo, ld=ld, L=rows[:, :nlo], invD=rows[:, nlo], D=Dv,
-                    levels=dsc.levels, n=n, factor_kernel_ms=dsc.factor_kernel_ms)
+                    levels=dsc.levels, n=n, factor_kernel_ms=dsc.factor_kernel_ms,
+                    factor_kernel=dsc.factor_kernel)
 
 
 def pcg_solve(problem: Problem, factor: Factor, F: torch.Tensor, x: torch.Tensor = None, rtol: float = 1e-10,

@@ -88,13 +88,20 @@ FACTOR_CASES = [(2, 12, 4, 4, 0), (2, 33, 4, 4, 0), (2, 40, 8, 8, 1), (2, 50, 6,
                 (3, 7, 2, 2, 0), (3, 10, 4, 4, 1), (3, 12, 6, 6, 2)]
 
 
-@pytest.mark.parametrize("d,N,Ta,Tb,seed", FACTOR_CASES)
-def test_factor_and_sweeps(d, N, Ta, Tb, seed):
+# the ILU(0) kernel variants: 2 (dataflow, the default where it applies) and
+# 1 (generic; the only one for the 3D stencils, whose hundreds of lower
+# offsets exceed what the dataflow kernel holds)
+KERNEL_CASES = [(2, 40, 8, 8, 1, k) for k in (2, 1)] + [(2, 50, 6, 3, 2, 2), (2, 33, 4, 4, 0, 1)]
+
+
+@pytest.mark.parametrize("d,N,Ta,Tb,seed,kernel", [c + (0,) for c in FACTOR_CASES] + KERNEL_CASES)
+def test_factor_and_sweeps(d, N, Ta, Tb, seed, kernel, monkeypatch):
     """Benchmark-family coefficients (evaluated independently on each side):
     same pattern, L and pivots to 1e-12, both sweeps to 1e-12."""
     from paper_2004_13961_amd.solver import Problem, Factor
     from paper_2004_13961_amd.workload import family_nodal
-    print("case factor d=%d N=%d Ta=%d Tb=%d" % (d, N, Ta, Tb), flush=True)
+    print("case factor d=%d N=%d Ta=%d Tb=%d kernel=%d" % (d, N, Ta, Tb, kernel), flush=True)
+    monkeypatch.setenv("LGP_FACTOR_KERNEL", str(kernel))
     B = gk.Basis(N)
     c = synth.coefficient_draws(d, 6, seed)
     a_o = owl.coefficient_a(c, B.x)
@@ -104,6 +111,9 @@ def test_factor_and_sweeps(d, N, Ta, Tb, seed):
     P = Problem(d, N, _dev(a_g).reshape(-1), _dev(b_g).reshape(-1))
     Fc = Factor(P, Ta, Tb)
     desc = Fc.describe()
+    print("factor kernel %d" % desc["factor_kernel"], flush=True)
+    if kernel:
+        assert desc["factor_kernel"] == kernel
     assert [tuple(o[:d]) for o in desc["offsets"]] == [tuple(o) for o in offs]
     nlo = desc["n_lower"]
     Lg = _host(desc["L"])
