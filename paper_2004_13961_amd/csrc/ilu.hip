@@ -1133,51 +1133,50 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
         // and leaves u_j = 0), so the load counter of each ring slot is static.
         // ring of PD steps in flight: the gathered values, the pair word of
         // each lane (~0u when the lane has no pair), the row offset of the step
+        // Pair words hold k (low 16 bits) and the slot l of the gathered
+        // entry L(i+delta_j, i+delta_j+delta_l) (high 16 bits). Lanes past
+        // a step's pair list take k = nlo+1 (u = 0) and l = the first step's
+        // slot: a real entry of the same row, published no later than the
+        // ones the step needs. A step whose row leaves the grid (or a
+        // padding step) gathers from the zero row.
         double g[PD][Q];
         unsigned pw[PD][Q];
         double dv[PD], mj[PD];
-        int jj[PD], rof[PD], rb[PD];
-        constexpr unsigned NOPAIR = 0xFFFFFFFFu;
-        auto kidx = [&](unsigned w2) { return w2 == NOPAIR ? nlo + 1 : (int)(w2 & 0xFFFFu); };
-        auto goff = [&](unsigned w2, int r0) { return w2 == NOPAIR ? zoff : r0 + (int)(w2 >> 16); };
+        int jj[PD], rb[PD];
+        const int k0 = __builtin_amdgcn_readfirstlane(st_s[0].x);
+        const unsigned padw = (unsigned)(nlo + 1) | ((unsigned)k0 << 16);
         auto issue = [&](int b, int s) {
             s -= npad;   // the ring runs over npad no-op steps first
             const bool live = s >= 0 && s < nsteps;
             const int sc = live ? s : 0;
-            const int4 S = st_s[sc];
-            const int dd = sd_s[sc];
-            const int sj = __builtin_amdgcn_readfirstlane(S.x);
-            const int slin = __builtin_amdgcn_readfirstlane(S.y);
-            const int pb = __builtin_amdgcn_readfirstlane(S.z);
-            const int pe = __builtin_amdgcn_readfirstlane(S.w);
-            const int ddu = __builtin_amdgcn_readfirstlane(dd);
-            const int dx = (ddu & 0xFF) - 128, dy = ((ddu >> 8) & 0xFF) - 128, dz = ((ddu >> 16) & 0xFF) - 128;
+            const int4 S = steps[sc];   // wave-uniform: scalar loads
+            const int dd = sdxyz[sc];
+            const int dx = (dd & 0xFF) - 128, dy = ((dd >> 8) & 0xFF) - 128, dz = ((dd >> 16) & 0xFF) - 128;
             const bool valid = live && (unsigned)(ix + dx) < (unsigned)n1 && (unsigned)(iy + dy) < (unsigned)n1 &&
                                (unsigned)(iz + dz) < (unsigned)n1;
-            jj[b] = live ? sj : nlo + 1;
-            const int r0 = (i + slin) * ldl;
+            jj[b] = live ? S.x : nlo + 1;
+            const int r0 = valid ? (i + S.y) * ldl : zoff;
             rb[b] = r0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                const int p = pb + lane + 64 * q;
-                const unsigned wd = pw_s[(p < pe) ? p : 0];
-                pw[b][q] = (valid && p < pe) ? wd : NOPAIR;
+                const int p = S.z + lane + 64 * q;
+                const unsigned wd = pw_s[(p < S.w) ? p : 0];
+                pw[b][q] = (p < S.w) ? wd : padw;
             }
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                g[b][q] = __hip_atomic_load(LD + goff(pw[b][q], r0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            rof[b] = valid ? r0 + nlo : zoff;
-            dv[b] = __hip_atomic_load(LD + rof[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                g[b][q] = __hip_atomic_load(LD + r0 + (pw[b][q] >> 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            dv[b] = __hip_atomic_load(LD + r0 + nlo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             mj[b] = u[jj[b]];   // M(i, i+delta_j) (0 when invalid); u_j is written only by step j
         };
         // A poll re-reads the values of a slot that are still sentinels (in
         // place, in the lanes that hold them), all before the first check:
         // one round trip however many values it waits for.
         auto reload = [&](int c) {
-            if (Sentinel<double>::is(dv[c])) dv[c] = ld_coh(LD + rof[c]);
+            if (Sentinel<double>::is(dv[c])) dv[c] = ld_coh(LD + rb[c] + nlo);
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                if (Sentinel<double>::is(g[c][q])) g[c][q] = ld_coh(LD + goff(pw[c][q], rb[c]));
+                if (Sentinel<double>::is(g[c][q])) g[c][q] = ld_coh(LD + rb[c] + (pw[c][q] >> 16));
         };
         auto pending = [&](int c) {
             bool bad = Sentinel<double>::is(dv[c]);
@@ -1186,19 +1185,27 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
             return bad;
         };
         double piv = 0.0;
+        // The step's sum is formed first; a sentinel among its values makes
+        // the sum NaN (sentinels are NaNs and u is finite), so one test of
+        // the wave total replaces a test per value. Then the values that
+        // are still sentinels are polled and the sum is formed again.
+        auto dot = [&](int b) {
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc += u[pw[b][q] & 0xFFFFu] * g[b][q];
+            return wave_sum_dpp(acc);
+        };
         auto consume = [&](int b) {
-            if (__builtin_expect(__any(pending(b)), 0)) {
+            double acc = dot(b);
+            if (__builtin_expect(__any(isnan(acc) | Sentinel<double>::is(dv[b])), 0)) {
                 // a step whose rows are not finished yet: poll its values
                 for (;;) {
                     reload(b);
                     if (!__any(pending(b))) break;
                     __builtin_amdgcn_s_sleep(1);
                 }
+                acc = dot(b);
             }
-            double acc = 0.0;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) acc += u[kidx(pw[b][q])] * g[b][q];
-            acc = wave_sum_dpp(acc);
             const double uj = mj[b] - acc;
             if (lane == 0) {
                 u[jj[b]] = uj;
@@ -1221,8 +1228,8 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
         // The last PD steps wait for the rows one and two levels back: the
         // hyperplane chain runs through them, so from here on the wave runs
         // at raised priority. The entries of the other steps are final:
-        // publish them first, then poll the late steps together (one round trip per poll instead of one per
-        // step), finish them and publish their entries, 1/D and D. Every
+        // publish them first, then poll the late steps together (one round
+        // trip per poll), finish them and publish their entries, 1/D and D. Every
         // store instruction runs in all lanes (the counters stay static):
         // a lane without an entry of its own repeats the store of another
         // lane (same address, same value) -- never a shared location, which
