@@ -797,6 +797,27 @@ __device__ inline double dpp_bcast15(double v) {
 __device__ inline float dpp_bcast15(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
 }
+// Wave total with DPP only: sums inside rows of 16 lanes, row_bcast15 adds
+// row 0 into row 1 and row 2 into row 3, row_bcast31 adds lane 31 into rows
+// 2 and 3; lane 63 then holds the total, read once into scalar registers.
+// The moves carry no old value (no register copies); lanes of the rows a
+// broadcast leaves out hold junk afterwards, but no later stage reads them
+// on the way to lane 63.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double wave_total_bcast(double v) {
+    v += dpp_mov<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141, 0xF>(v);   // row_half_mirror
+    v += dpp_mov<0x140, 0xF>(v);   // row_mirror
+    v += dpp_mov<0x142, 0xA>(v);   // row_bcast15 into rows 1, 3
+    v += dpp_mov<0x143, 0xC>(v);   // row_bcast31 into rows 2, 3
+    return lane_val(v, 63);
+}
 
 template <typename T, int SL, int D, int NW, bool REV, bool SCALE, bool STAGE>
 __device__ inline void pair_walk(int n1, int64_t n, int ldl, int first, int lbase, int Hx, int Hy, int Wd,
@@ -1026,8 +1047,11 @@ __global__ void reset_kernel(unsigned* p, int count) {
 //     u_j when offset(k) - offset(j) is a lower offset) that visits first
 //     the offsets whose rows finished longest ago. The loads of the next PD
 //     steps are in flight while a step is reduced.
-//   * The pivot accumulates u_j^2 / D(i + delta_j) step by step, so the row
-//     is complete right after its last step.
+//   * Pair words hold byte offsets: k*8 (into the row's u vector in LDS) in
+//     the low half, l*8 (into the gathered row) in the high half, so a
+//     gather address is a scalar row pointer plus one shifted lane value.
+//   * The pivot sum over u_j^2 / D(i + delta_j) is formed once per row,
+//     from the LDS vectors, just before the last steps.
 //   * Each wave works on its own rows; the waves of a workgroup share the
 //     step and pair tables in LDS.
 template <int Q, int PD>
@@ -1041,9 +1065,9 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
     int4* st_s = (int4*)smem_raw;                 // [nsteps]
     int4* of_s = st_s + nsteps;                   // [nlo + 1] offsets (dx, dy, dz, linear)
     int* sd_s = (int*)(of_s + nlo + 1);           // [nsteps]
-    unsigned* pw_s = (unsigned*)(sd_s + nsteps);  // [npairs]
+    unsigned* pw_s = (unsigned*)(sd_s + nsteps);  // [npairs + 64 Q]: reads past a list stay inside
     const size_t tab_bytes =
-        (((size_t)nsteps * 20 + (size_t)(nlo + 1) * 16 + (size_t)npairs * 4) + 15) & ~(size_t)15;
+        (((size_t)nsteps * 20 + (size_t)(nlo + 1) * 16 + (size_t)(npairs + 64 * Q) * 4) + 15) & ~(size_t)15;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1056,7 +1080,7 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
         sd_s[e] = sdxyz[e];
     }
     for (int e = tid; e <= nlo; e += blockDim.x) of_s[e] = offs[e];
-    for (int e = tid; e < npairs; e += blockDim.x) pw_s[e] = pairw[e];
+    for (int e = tid; e < npairs + 64 * Q; e += blockDim.x) pw_s[e] = e < npairs ? pairw[e] : 0u;
     __syncthreads();
 
     const int W = 2 * h + 1;
@@ -1141,10 +1165,11 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
         // padding step) gathers from the zero row.
         double g[PD][Q];
         unsigned pw[PD][Q];
-        double dv[PD], mj[PD];
+        double dv[PD];
         int jj[PD], rb[PD];
         const int k0 = __builtin_amdgcn_readfirstlane(st_s[0].x);
-        const unsigned padw = (unsigned)(nlo + 1) | ((unsigned)k0 << 16);
+        const unsigned padw = (unsigned)(nlo + 1) * 8u | ((unsigned)k0 * 8u << 16);
+        const char* ub = (const char*)u;
         auto issue = [&](int b, int s) {
             s -= npad;   // the ring runs over npad no-op steps first
             const bool live = s >= 0 && s < nsteps;
@@ -1157,17 +1182,19 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
             jj[b] = live ? S.x : nlo + 1;
             const int r0 = valid ? (i + S.y) * ldl : zoff;
             rb[b] = r0;
+            const int np = S.w - S.z;
+            const unsigned* pwp = pw_s + S.z + lane;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                const int p = S.z + lane + 64 * q;
-                const unsigned wd = pw_s[(p < S.w) ? p : 0];
-                pw[b][q] = (p < S.w) ? wd : padw;
+                const unsigned wd = pwp[64 * q];
+                pw[b][q] = (lane + 64 * q < np) ? wd : padw;
             }
+            const char* rowp = (const char*)(LD + r0);
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                g[b][q] = __hip_atomic_load(LD + r0 + (pw[b][q] >> 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                g[b][q] = __hip_atomic_load((const double*)(rowp + (pw[b][q] >> 16)), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_WORKGROUP);
             dv[b] = __hip_atomic_load(LD + r0 + nlo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            mj[b] = u[jj[b]];   // M(i, i+delta_j) (0 when invalid); u_j is written only by step j
         };
         // A poll re-reads the values of a slot that are still sentinels (in
         // place, in the lanes that hold them), all before the first check:
@@ -1176,7 +1203,8 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
             if (Sentinel<double>::is(dv[c])) dv[c] = ld_coh(LD + rb[c] + nlo);
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                if (Sentinel<double>::is(g[c][q])) g[c][q] = ld_coh(LD + rb[c] + (pw[c][q] >> 16));
+                if (Sentinel<double>::is(g[c][q]))
+                    g[c][q] = ld_coh((const double*)((const char*)(LD + rb[c]) + (pw[c][q] >> 16)));
         };
         auto pending = [&](int c) {
             bool bad = Sentinel<double>::is(dv[c]);
@@ -1184,7 +1212,6 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
             for (int q = 0; q < Q; ++q) bad |= Sentinel<double>::is(g[c][q]);
             return bad;
         };
-        double piv = 0.0;
         // The step's sum is formed first; a sentinel among its values makes
         // the sum NaN (sentinels are NaNs and u is finite), so one test of
         // the wave total replaces a test per value. Then the values that
@@ -1192,10 +1219,11 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
         auto dot = [&](int b) {
             double acc = 0.0;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) acc += u[pw[b][q] & 0xFFFFu] * g[b][q];
-            return wave_sum_dpp(acc);
+            for (int q = 0; q < Q; ++q) acc += *(const double*)(ub + (pw[b][q] & 0xFFFFu)) * g[b][q];
+            return wave_total_bcast(acc);
         };
-        auto consume = [&](int b) {
+        auto consume = [&](int b) {   // returns u_j
+            const double mj = u[jj[b]];   // M(i, i+delta_j) (0 when invalid); u_j is written only by step j
             double acc = dot(b);
             if (__builtin_expect(__any(isnan(acc) | Sentinel<double>::is(dv[b])), 0)) {
                 // a step whose rows are not finished yet: poll its values
@@ -1206,12 +1234,27 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
                 }
                 acc = dot(b);
             }
-            const double uj = mj[b] - acc;
+            const double uj = mj - acc;
             if (lane == 0) {
                 u[jj[b]] = uj;
                 w[jj[b]] = dv[b];
             }
-            piv += uj * uj * dv[b];
+            return uj;
+        };
+        // sum of u_j^2 / D(i + delta_j) over the steps done so far (late
+        // steps excluded); u and w are zero at the padding index
+        auto pivot_sum = [&]() {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < Q; ++m) {
+                const int k = lane + 64 * m;
+                bool own = k < nlo;
+#pragma unroll
+                for (int b = 0; b < PD; ++b) own &= (k != jj[b]);
+                const int kk = own ? k : nlo + 1;
+                acc += u[kk] * u[kk] * w[kk];
+            }
+            return wave_total_bcast(acc);
         };
 #pragma unroll
         for (int b = 0; b < PD; ++b) issue(b, b);
@@ -1248,6 +1291,7 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
                 st_coh(Li + kk, Sentinel<double>::clean(u[kk] * w[kk]));
             }
         }
+        double piv = pivot_sum();
         for (;;) {
             bool still = false;
 #pragma unroll
@@ -1261,7 +1305,10 @@ __global__ __launch_bounds__(1024) void ilu_factor2_kernel(
             __builtin_amdgcn_s_sleep(1);
         }
 #pragma unroll
-        for (int b = 0; b < PD; ++b) consume(b);
+        for (int b = 0; b < PD; ++b) {
+            const double uj = consume(b);   // zero for padding steps
+            piv += uj * uj * dv[b];
+        }
         // L(i, i+delta_k) = u_k / D(i+delta_k); D(i) = M(i,i) - sum_k u_k L(i, i+delta_k).
         // D(i) is the same in every lane; taking it from lane 0 makes the
         // pivot test and the stores below wave-uniform.
@@ -1422,7 +1469,7 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
             st4[4 * s2 + 0] = j;
             st4[4 * s2 + 1] = off4[4 * j + 3];
             st4[4 * s2 + 2] = (int)pw.size();
-            for (int e = ptr[j]; e < ptr[j + 1]; ++e) pw.push_back((unsigned)pk[e] | ((unsigned)pl[e] << 16));
+            for (int e = ptr[j]; e < ptr[j + 1]; ++e) pw.push_back((unsigned)pk[e] * 8u | ((unsigned)pl[e] * 8u << 16));
             st4[4 * s2 + 3] = (int)pw.size();
             sd[s2] = (F.offs[3 * j] + 128) | ((F.offs[3 * j + 1] + 128) << 8) | ((F.offs[3 * j + 2] + 128) << 16);
         }
@@ -1495,7 +1542,7 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
     // element offsets, pair indices in 16 bits
     constexpr int FQ = 4, FPD = 4;
     const size_t tab_bytes =
-        (((size_t)F.nlo * 20 + (size_t)(F.nlo + 1) * 16 + (size_t)F.npairs * 4) + 15) & ~(size_t)15;
+        (((size_t)F.nlo * 20 + (size_t)(F.nlo + 1) * 16 + (size_t)(F.npairs + 64 * FQ) * 4) + 15) & ~(size_t)15;
     const size_t wave_bytes = (size_t)(2 * F.nlo + 4) * 8;
     int wpb = 16;
     while (wpb > 4 && tab_bytes + wpb * wave_bytes > 150 * 1024) wpb /= 2;

@@ -119,7 +119,7 @@ struct Factor {
     int maxpairs;     // largest pair list of one lower offset
     int* steps;       // [nlo][4] {j, linear offset, first pair, end pair} in dataflow order
     int* sdxyz;       // [nlo] packed (dx+128) | (dy+128) << 8 | (dz+128) << 16 of each step
-    unsigned* pairw;  // [npairs] k | l << 16, grouped by step
+    unsigned* pairw;  // [npairs] k*8 | (l*8) << 16 (byte offsets), grouped by step
     int maxlev;       // number of hyperplane levels
     int* lev;         // [maxlev + 1] first ticket of each level, then [maxlev] fill counters
     int* runs;        // [nruns][4] runs of lower offsets with equal (dy, dz): {kb, ke, dx_first, dx_last}
