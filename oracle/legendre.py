@@ -39,29 +39,45 @@ def legendre_deriv_table(nmax: int, x) -> np.ndarray:
     return dP
 
 
+def _legendre_pair(m: int, x):
+    """(L_{m-1}(x), L_m(x)) by the three-term recurrence, in the dtype of x."""
+    p0 = np.ones_like(x)
+    p1 = x.copy()
+    for k in range(1, m):
+        p0, p1 = p1, ((2 * k + 1) * x * p1 - k * p0) / (k + 1)
+    return p0, p1
+
+
 def gauss_legendre(N: int):
     """Nodes x_0 < ... < x_N (roots of L_{N+1}, Sec. 2.2) and weights.
 
     Newton's method on the recurrence from the classical initial guess
     x ~ cos(pi (i + 3/4) / (N + 3/2)) (Tricomi's asymptotic first term),
     weights w_i = 2 / ((1 - x_i^2) L'_{N+1}(x_i)^2).
+
+    The iteration and the weight formula run in extended precision
+    (numpy longdouble) and are rounded to FP64 at the end: a node off by one
+    FP64 unit near an end of the interval moves its weight by about
+    2 x / (1 - x^2) units, i.e. up to ~2 q^2 * 1e-16 relative (2e-10 at
+    q = 1025), which the operator then carries.
     """
     m = N + 1
     i = np.arange(m)
-    x = np.cos(np.pi * (i + 0.75) / (m + 0.5))
+    x = np.cos(np.pi * (i + 0.75) / (m + 0.5)).astype(np.longdouble)
+    eps = np.finfo(np.longdouble).eps
     for _ in range(100):
-        P = legendre_table(m, x)
+        pm1, pm = _legendre_pair(m, x)
         # L'_m from (1 - x^2) L'_m = m (L_{m-1} - x L_m)
-        dp = m * (P[m - 1] - x * P[m]) / (1.0 - x * x)
-        dx = P[m] / dp
+        dp = m * (pm1 - x * pm) / (1 - x * x)
+        dx = pm / dp
         x = x - dx
-        if np.max(np.abs(dx)) < 1e-16:
+        if np.max(np.abs(dx)) < 4 * eps:
             break
-    P = legendre_table(m, x)
-    dp = m * (P[m - 1] - x * P[m]) / (1.0 - x * x)
-    w = 2.0 / ((1.0 - x * x) * dp * dp)
+    pm1, pm = _legendre_pair(m, x)
+    dp = m * (pm1 - x * pm) / (1 - x * x)
+    w = 2 / ((1 - x * x) * dp * dp)
     order = np.argsort(x)
-    return x[order], w[order]
+    return x[order].astype(np.float64), w[order].astype(np.float64)
 
 
 def bdlt(c: np.ndarray, P: np.ndarray) -> np.ndarray:

@@ -83,6 +83,20 @@ def test_M_spd_symmetric_and_pattern(d, N, T):
     assert np.max(np.abs(H - H2)) < 1e-13 * np.max(np.abs(M))
 
 
+@pytest.mark.parametrize("d,N,T", [(2, 12, 4), (3, 6, 2)])
+def test_M_row_entries_match_dense(d, N, T):
+    """The term-by-term row entries (used by the full-size sampled checks)
+    equal the dense Kronecker-form M, out-of-grid columns included as 0."""
+    B, a, b, ah, bh = _config_problem(d, N, T)
+    M = pc.dense_M(d, N - 1, ah, bh)
+    offs = pc.stencil_offsets(ah, bh)
+    H2 = ilu.stencil_rows_from_dense(M, d, N - 1, offs)
+    n = (N - 1) ** d
+    for row in (0, n // 3, n // 2 + 1, n - 1):
+        e = pc.M_row_entries(d, N - 1, ah, bh, row, offs)
+        assert np.max(np.abs(e - H2[row])) < 1e-13 * np.max(np.abs(M))
+
+
 def test_config_pattern_is_box_minus_corners():
     for (d, N, T, J) in [(2, 40, 4, 6), (2, 40, 8, 12), (3, 20, 6, 6)]:
         B, a, b, ah, bh = _config_problem(d, N, T, J=J)
