@@ -115,6 +115,54 @@ def matvec_sumfact(d: int, N: int, a_nodes, b_nodes, u, basis: Basis = None):
     return y.reshape(-1)
 
 
+def matvec_sumfact_ext(d: int, N: int, a_nodes, b_nodes, u, basis: Basis = None):
+    """matvec_sumfact in extended precision (numpy longdouble, 64-bit
+    mantissa): the same nodes, weights and coefficient values (FP64 inputs,
+    widened), the tables phi_k, phi_k' rebuilt by the recurrence in extended
+    precision, the same steps. A reference for large N, where the FP64
+    product itself drifts by ~N^2 * 1e-16 relative (the derivative tables
+    grow like k). Slow: minutes at N = 1024 in 2D."""
+    B = basis if basis is not None else Basis(N)
+    LD = np.longdouble
+    x = B.x.astype(LD)
+    m = N + 2
+    P = np.zeros((m + 1, B.q), dtype=LD)
+    P[0] = 1
+    P[1] = x
+    for n in range(1, m):
+        P[n + 1] = ((2 * n + 1) * x * P[n] - n * P[n - 1]) / (n + 1)
+    k = np.arange(B.n1)
+    Phi = (P[k] - P[k + 2]).T
+    Dt = (-(2 * k + 3)[:, None].astype(LD) * P[k + 1]).T
+    w = B.w.astype(LD)
+    W = w
+    for _ in range(d - 1):
+        W = np.multiply.outer(w, W)
+    U = np.asarray(u, dtype=np.float64).astype(LD).reshape((B.n1,) * d)
+    wa = W * np.asarray(a_nodes, dtype=np.float64).astype(LD).reshape((B.q,) * d)
+    wb = W * np.asarray(b_nodes, dtype=np.float64).astype(LD).reshape((B.q,) * d)
+
+    def along(T, arr, ax):
+        return np.moveaxis(np.tensordot(T, arr, axes=(1, ax)), 0, ax)
+
+    def fwd(deriv_axis):
+        out = U
+        for ax in range(d):
+            out = along(Dt if d - 1 - ax == deriv_axis else Phi, out, ax)
+        return out
+
+    def bwd(g, deriv_axis):
+        out = g
+        for ax in range(d):
+            out = along((Dt if d - 1 - ax == deriv_axis else Phi).T, out, ax)
+        return out
+
+    y = bwd(wb * fwd(None), None)
+    for i in range(d):
+        y = y + bwd(wa * fwd(i), i)
+    return y.reshape(-1).astype(np.float64)
+
+
 def load_vector(d: int, N: int, f_nodes, basis: Basis = None) -> np.ndarray:
     """F_k = (I_N f, psi_k) = sum_nodes W f psi_k (reading: the same
     (N+1)-point rule as the operator; the paper leaves the rule open)."""

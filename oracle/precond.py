@@ -196,9 +196,12 @@ def dense_M(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray) -> np.ndarray:
 
 
 def M_row_entries(d: int, n1: int, ahat, bhat, row_idx, offsets,
-                  S=None, Mm=None):
+                  S=None, Mm=None, return_abs: bool = False):
     """Entries M(row, row+delta) for the listed offsets (0 outside the grid),
-    computed term by term from the 1D factors (for sampled-row checks)."""
+    computed term by term from the 1D factors (for sampled-row checks).
+    With return_abs, also the sums of the magnitudes of the terms and of the
+    1D factor products alone (the scales of the rounding in any evaluation
+    of the entry, and of its sensitivity to the series coefficients)."""
     T = max(ahat.shape[0], bhat.shape[0]) - 1
     if S is None:
         S, Mm = band_factors(n1, T)
@@ -209,6 +212,8 @@ def M_row_entries(d: int, n1: int, ahat, bhat, row_idx, offsets,
         coords.append(r % n1)
         r //= n1
     out = np.zeros(len(offsets))
+    mag = np.zeros(len(offsets))
+    pmag = np.zeros(len(offsets))
     for oi, off in enumerate(offsets):
         col = [coords[k] + off[k] for k in range(d)]
         if any(c < 0 or c >= n1 for c in col):
@@ -222,14 +227,20 @@ def M_row_entries(d: int, n1: int, ahat, bhat, row_idx, offsets,
                     F = S if k == s_dir else Mm
                     prod *= F[deg[k], coords[k], col[k]]
                 val += prod
+                mag[oi] += abs(prod)
+                if ahat[idx] != 0.0:
+                    pmag[oi] += abs(prod / ahat[idx])
         for idx in np.ndindex(*bhat.shape):
             deg = idx[::-1]
             prod = bhat[idx]
             for k in range(d):
                 prod *= Mm[deg[k], coords[k], col[k]]
             val += prod
+            mag[oi] += abs(prod)
+            if bhat[idx] != 0.0:
+                pmag[oi] += abs(prod / bhat[idx])
         out[oi] = val
-    return out
+    return (out, mag, pmag) if return_abs else out
 
 
 def pattern_mask(d: int, n1: int, offsets) -> np.ndarray:

@@ -1055,7 +1055,7 @@ __global__ void reset_kernel(unsigned* p, int count) {
 //   * Each wave works on its own rows; the waves of a workgroup share the
 //     step and pair tables in LDS.
 template <int Q, int PD>
-__global__ __launch_bounds__(1024) void ilu_factor2_kernel(
+__global__ __launch_bounds__(768) void ilu_factor2_kernel(
     int d, int n1, int64_t n, int nlo, int ldl, int nsteps, int npairs, int T, int h,
     const int4* __restrict__ offs, const int4* __restrict__ steps, const int* __restrict__ sdxyz,
     const unsigned* __restrict__ pairw, const int* __restrict__ row_order, const double* __restrict__ band,
@@ -1544,8 +1544,10 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
     const size_t tab_bytes =
         (((size_t)F.nlo * 20 + (size_t)(F.nlo + 1) * 16 + (size_t)(F.npairs + 64 * FQ) * 4) + 15) & ~(size_t)15;
     const size_t wave_bytes = (size_t)(2 * F.nlo + 4) * 8;
-    int wpb = 16;
-    while (wpb > 4 && tab_bytes + wpb * wave_bytes > 150 * 1024) wpb /= 2;
+    // 12 waves per workgroup: the register budget of 3 waves per SIMD keeps
+    // the step ring free of spills, which beats a fourth wave per SIMD
+    int wpb = 12;
+    while (wpb > 3 && tab_bytes + wpb * wave_bytes > 150 * 1024) wpb /= 2;
     // LGP_FACTOR_KERNEL = 1 or 2 restricts the choice to that kernel where it
     // applies (for tests of both); 0 or unset takes the dataflow kernel (2)
     // where it applies, else the generic one (1)

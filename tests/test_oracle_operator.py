@@ -62,6 +62,23 @@ def test_three_matvec_routes_agree(d, N):
     assert np.linalg.eigvalsh(K).min() > 0
 
 
+@pytest.mark.parametrize("d,N", [(2, 8), (2, 40), (3, 7)])
+def test_extended_matvec_matches_dense_and_fp64(d, N):
+    """The extended-precision product (the reference at the benchmark sizes)
+    agrees with the dense node-sum operator and with the FP64 product."""
+    q = N + 1
+    rng = np.random.default_rng(7 * d + N)
+    a = 1.0 + rng.uniform(0, 1, (q,) * d)
+    b = rng.uniform(0, 1, (q,) * d)
+    u = rng.uniform(-1, 1, (N - 1) ** d)
+    ye = gk.matvec_sumfact_ext(d, N, a, b, u)
+    y0 = gk.dense_operator(d, N, a, b) @ u
+    y1 = gk.matvec_sumfact(d, N, a, b, u)
+    nrm = np.linalg.norm(y0)
+    assert np.linalg.norm(ye - y0) < 1e-13 * nrm
+    assert np.linalg.norm(ye - y1) < 1e-14 * nrm
+
+
 def test_matvec_symmetry_large():
     d, N = 2, 48
     q = N + 1
