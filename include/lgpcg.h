@@ -40,7 +40,7 @@ typedef enum {
     LGP_OK = 0,
     LGP_E_ARG = 1,        /* bad argument: d not in {2,3}, N < 2, null pointer, T < 0 */
     LGP_E_NOMEM = 2,      /* caller buffer smaller than the size query returned */
-    LGP_E_COEF = 3,       /* a <= 0, b < 0 or a non-finite value at a node */
+    LGP_E_COEF = 3,       /* a <= 0 or a non-finite value at a node, or min b <= -(d pi^2/4) min a */
     LGP_E_ILU_PIVOT = 4,  /* ILU(0) pivot <= 0 or non-finite (Alg. 2 assumes existence) */
     LGP_E_NOCONV = 5,     /* max_iter reached before the stop rule of Alg. 1 */
     LGP_E_BREAKDOWN = 6,  /* p'Kp <= 0 or r'z <= 0 in PCG */
@@ -69,9 +69,12 @@ size_t lgp_problem_bytes(int d, int N);
 
 /* Build the operator K = A + B of Sec. 3 / Sec. 4.3 from nodal coefficient
  * values a_nodes, b_nodes (device, (N+1)^d doubles each, x fastest). The
- * model problem requires a > 0 and b >= 0 (Sec. 3): the call checks every
- * node and returns LGP_E_COEF otherwise (it synchronises `stream` for that
- * check). The nodal arrays are copied; buf (device, buf_bytes >=
+ * model problem of Sec. 3 asks a > 0 and b >= 0, but the paper's own test
+ * coefficients (Sec. 5.2) take b < 0 near a corner; what the method needs
+ * is a coercive form, which holds when min b > -(d pi^2/4) min a (Poincare
+ * inequality on (-1,1)^d). The call checks a > 0 and finiteness at every
+ * node and that bound, and returns LGP_E_COEF otherwise (it synchronises
+ * `stream` for that check). The nodal arrays are copied; buf (device, buf_bytes >=
  * lgp_problem_bytes) holds tables, weighted coefficients and matvec
  * scratch and must outlive the handle. */
 lgp_status lgp_build_problem(int d, int N, const double* a_nodes, const double* b_nodes,
@@ -109,9 +112,27 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store,
                         void* buf, size_t buf_bytes, void* stream, lgp_factor* out);
 void lgp_destroy_factor(lgp_factor m);
 
+/* The constant-coefficient preconditioner of the comparison method PCG-I
+ * (Sec. 5.2): a and b replaced by their series truncated at T = 0 (their
+ * weighted means c_a, c_b, Sec. 4.1), i.e.
+ *   K0 = c_a (S (x) M + M (x) S) + c_b M (x) M      (2D; three terms in 3D)
+ * with the exact 1D stiffness S = diag(4k+6) and the pentadiagonal 1D mass M
+ * of the compact basis (Sec. 2.1, 3). The paper solves K0 by a fast direct
+ * method; here it is inverted exactly by matrix diagonalisation (generalized
+ * eigenvectors of (M, S), computed once per N on the host in FP64 and
+ * cached; 2d dense contractions per application on the GPU). The handle
+ * works with lgp_precond_apply (z = K0^{-1} r) and with lgp_pcg_solve for
+ * inner = LGP_F64 (PCG-I); lgp_ilu_forward, lgp_ilu_backward and
+ * lgp_factor_describe return LGP_E_UNSUPPORTED for it, and so does
+ * lgp_pcg_solve with a low-precision inner solve. Buffer: device bytes from
+ * lgp_factor_const_bytes, owned by the caller. Synchronises `stream`. */
+size_t lgp_factor_const_bytes(lgp_problem p);
+lgp_status lgp_factor_const(lgp_problem p, void* buf, size_t buf_bytes, void* stream, lgp_factor* out);
+
 /* One-step preconditioner application of Sec. 4.2: z = U^{-1} L^{-1} r
- * (forward substitution Alg. 3, then backward substitution Alg. 4). r, z
- * device (N-1)^d doubles; must not alias. */
+ * (forward substitution Alg. 3, then backward substitution Alg. 4); for a
+ * handle from lgp_factor_const, z = K0^{-1} r. r, z device (N-1)^d doubles;
+ * must not alias. */
 lgp_status lgp_precond_apply(lgp_factor m, const double* r, double* z, void* stream);
 /* The two halves separately: y = L^{-1} r (Alg. 3) and z = U^{-1} y (Alg. 4). */
 lgp_status lgp_ilu_forward(lgp_factor m, const double* r, double* y, void* stream);

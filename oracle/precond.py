@@ -310,3 +310,75 @@ def stencil_rows(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray, offsets,
                    + term(A, Sd[2], Md[1], Md[0]) + term(Bc, Md[2], Md[1], Md[0]))
         H[:, o] = val.reshape(-1)
     return H
+
+
+# --------------------------------------------------------------- PCG-I -----
+def constant_coefficients(a_nodes, b_nodes, basis: Basis):
+    """(c_a, c_b): the series of a and b truncated at T = 0 (Sec. 4.1), the
+    preconditioner of the comparison method PCG-I (Sec. 5.2)."""
+    ah, bh = series_pair(a_nodes, b_nodes, basis, 0, 0)
+    return float(ah.reshape(-1)[0]), float(bh.reshape(-1)[0])
+
+
+def constant_operator_dense(d: int, N: int, ca: float, cb: float) -> np.ndarray:
+    """K0 = c_a sum_dir (S in that direction, M elsewhere) + c_b (M x ... x M)
+    from the closed-form 1D stiffness and mass of the compact basis."""
+    from .galerkin import constant_coefficient_factors
+    S1, M1 = constant_coefficient_factors(N)
+    K = cb * _kron_all([M1] * d)
+    for i in range(d):
+        mats = [M1] * d
+        mats[i] = S1
+        K = K + ca * _kron_all(mats)
+    return K
+
+
+def constant_solve(d: int, N: int, ca: float, cb: float, r) -> np.ndarray:
+    """z = K0^{-1} r through the generalized eigenvectors of (M, S) in 1D
+    (scipy's symmetric-definite eigensolver): E^T S E = I, E^T M E = diag(lam),
+    so K0 is diagonal in the tensor basis E x ... x E."""
+    import scipy.linalg as sla
+    from .galerkin import constant_coefficient_factors
+    S1, M1 = constant_coefficient_factors(N)
+    lam, E = sla.eigh(M1, S1)
+    n1 = N - 1
+    R = np.asarray(r, dtype=np.float64).reshape((n1,) * d)
+    V = R
+    for ax in range(d):
+        V = lg.apply_along(E.T, V, ax)
+    grids = np.meshgrid(*([lam] * d), indexing="ij")
+    prod = np.ones_like(grids[0])
+    for g in grids:
+        prod = prod * g
+    pair = np.zeros_like(grids[0])
+    for i in range(d):
+        term = np.ones_like(grids[0])
+        for k in range(d):
+            if k != i:
+                term = term * grids[k]
+        pair = pair + term
+    V = V / (ca * pair + cb * prod)
+    for ax in range(d):
+        V = lg.apply_along(E, V, ax)
+    return V.reshape(-1)
+
+
+def constant_apply(d: int, N: int, ca: float, cb: float, z) -> np.ndarray:
+    """K0 z from the 1D factors (one direction at a time)."""
+    from .galerkin import constant_coefficient_factors
+    S1, M1 = constant_coefficient_factors(N)
+    n1 = N - 1
+    Z = np.asarray(z, dtype=np.float64).reshape((n1,) * d)
+
+    def chain(mats):
+        out = Z
+        for ax in range(d):
+            out = lg.apply_along(mats[ax], out, ax)
+        return out
+
+    y = cb * chain([M1] * d)
+    for i in range(d):
+        mats = [M1] * d
+        mats[i] = S1
+        y = y + ca * chain(mats)
+    return y.reshape(-1)

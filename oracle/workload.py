@@ -74,3 +74,20 @@ def rhs_f(c: np.ndarray, xs) -> np.ndarray:
         da_i = lg.legendre_series_grad_eval(c, [xs] * d, i)
         grad_dot += da_i * du_i
     return -a * lap - grad_dot + b * u
+
+
+def paper_example(case: str, d: int, xs):
+    """(a, b) of the paper's variable-coefficient examples (Sec. 5.2):
+    Example 2 (d = 2) and Example 3 (d = 3); case "a": a = (2|x|^2 + 1)^4,
+    b = cos(sum_i x_i); case "b": a = exp(2 sum_i x_i), b = 0."""
+    X = _grid(xs, d)
+    s = sum(X)
+    if case == "a":
+        a = (2.0 * sum(Xi ** 2 for Xi in X) + 1.0) ** 4
+        b = np.cos(s)
+    elif case == "b":
+        a = np.exp(2.0 * s)
+        b = np.zeros_like(s)
+    else:
+        raise ValueError(case)
+    return a, b

@@ -27,7 +27,7 @@ const char* lgp_status_str(lgp_status s) {
         case LGP_OK: return "ok";
         case LGP_E_ARG: return "invalid argument";
         case LGP_E_NOMEM: return "buffer too small";
-        case LGP_E_COEF: return "coefficient violates a > 0, b >= 0 at a node";
+        case LGP_E_COEF: return "coefficient violates a > 0 at a node, or b below the coercivity bound";
         case LGP_E_ILU_PIVOT: return "ILU(0) pivot <= 0 or not finite";
         case LGP_E_NOCONV: return "no convergence within max_iter";
         case LGP_E_BREAKDOWN: return "PCG breakdown (p'Kp <= 0 or r'z <= 0)";
@@ -326,18 +326,42 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
 
 void lgp_destroy_factor(lgp_factor m) { delete m; }
 
+size_t lgp_factor_const_bytes(lgp_problem p) {
+    if (!p) return 0;
+    return const_factor_bytes(p->P);
+}
+
+lgp_status lgp_factor_const(lgp_problem p, void* buf, size_t buf_bytes, void* stream, lgp_factor* out) {
+    if (!out) return LGP_E_ARG;
+    *out = nullptr;
+    if (!p || !buf) return LGP_E_ARG;
+    if (buf_bytes < lgp_factor_const_bytes(p)) return LGP_E_NOMEM;
+    lgp_factor_s* hF = new (std::nothrow) lgp_factor_s();
+    if (!hF) return LGP_E_NOMEM;
+    lgp_status st = const_factor_build(hF->F, p->P, buf, buf_bytes, (hipStream_t)stream);
+    if (st != LGP_OK) {
+        delete hF;
+        return st;
+    }
+    *out = hF;
+    return LGP_OK;
+}
+
 lgp_status lgp_ilu_forward(lgp_factor m, const double* r, double* y, void* stream) {
     if (!m || !r || !y || r == y) return LGP_E_ARG;
+    if (m->F.kind != 0) return LGP_E_UNSUPPORTED;
     return sweep(m->F, false, r, y, (hipStream_t)stream);
 }
 
 lgp_status lgp_ilu_backward(lgp_factor m, const double* y, double* z, void* stream) {
     if (!m || !y || !z || y == z) return LGP_E_ARG;
+    if (m->F.kind != 0) return LGP_E_UNSUPPORTED;
     return sweep(m->F, true, y, z, (hipStream_t)stream);
 }
 
 lgp_status lgp_precond_apply(lgp_factor m, const double* r, double* z, void* stream) {
     if (!m || !r || !z || r == z) return LGP_E_ARG;
+    if (m->F.kind == 1) return const_apply(m->F, r, z, (hipStream_t)stream);
     lgp_status st = sweep(m->F, false, r, m->F.y_tmp, (hipStream_t)stream);
     if (st != LGP_OK) return st;
     return sweep(m->F, true, m->F.y_tmp, z, (hipStream_t)stream);
@@ -345,6 +369,7 @@ lgp_status lgp_precond_apply(lgp_factor m, const double* r, double* z, void* str
 
 lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out) {
     if (!m || !out) return LGP_E_ARG;
+    if (m->F.kind != 0) return LGP_E_UNSUPPORTED;
     const Factor& F = m->F;
     out->d = F.d;
     out->N = F.n1 + 1;

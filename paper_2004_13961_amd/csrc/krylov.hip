@@ -275,6 +275,7 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
     const bool mixed = (o.inner != LGP_F64);
     SolveWS S;
     if (plan_ws(S, n, mixed, ws) > ws_bytes) return LGP_E_NOMEM;
+    if (mixed && M.kind != 0) return LGP_E_UNSUPPORTED;
     if (mixed && !M.has32) return LGP_E_ARG;
     lgp_status st;
     info->iters = 0;
@@ -331,6 +332,7 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
                 n, x, S.r, S.z, S.p, S.w, S, o.max_iter - total, check_every,
                 [&](const double* pp, double* ww) { return matvec_f64(P, pp, ww, s); },
                 [&](const double* rr_, double* zz) {
+                    if (M.kind == 1) return const_apply(M, rr_, zz, s);
                     lgp_status a = sweep(M, false, rr_, M.y_tmp, s, S.fl);
                     if (a != LGP_OK) return a;
                     return sweep(M, true, M.y_tmp, zz, s, S.fl);

@@ -79,6 +79,7 @@ struct Problem {
     double* s0; double* s1; double* s2; double* s3;
     size_t s0n, s1n, s2n, s3n;
     int* flag;      // device status flag
+    double* cmin;   // [2*256 + 2] per-block minima of a and b, then (min a, min b)
     size_t bytes;
 };
 
@@ -126,6 +127,15 @@ struct Factor {
     int nruns;
     float factor_kernel_ms;   // duration of the ILU(0) kernel of the last build (HIP events)
     int factor_kernel;        // 2: dataflow kernel, 1: generic kernel
+    // kind 1: the constant-coefficient operator solved exactly (matrix
+    // diagonalisation); only P, d, n1, n and the cc* fields are used
+    int kind = 0;
+    double* ccE = nullptr;     // [n1][n1] generalized eigenvectors, E^T S E = I, E^T M E = diag(lam)
+    double* ccLam = nullptr;   // [n1]
+    double* ccInv = nullptr;   // [n1^d] 1 / eigenvalues of the transformed operator
+    double* ccT1 = nullptr;    // [n1^d] scratch
+    double* ccT2 = nullptr;    // [n1^d] scratch
+    double* ccPart = nullptr;  // [2*256 + 2] partial sums, then (c_a, c_b)
     double* y_tmp;    // [n] intermediate of precond_apply
     bool has32;
     size_t bytes;
@@ -133,6 +143,9 @@ struct Factor {
 
 size_t plan_factor(Factor& F, void* buf, bool with32);
 lgp_status factor_build(Factor& F, hipStream_t s);
+size_t const_factor_bytes(const Problem& P);
+lgp_status const_factor_build(Factor& F, Problem& P, void* buf, size_t bytes, hipStream_t s);
+lgp_status const_apply(Factor& F, const double* r, double* z, hipStream_t s);
 lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStream_t s,
                  const int* stop = nullptr);
 lgp_status sweep32(Factor& F, bool backward, const float* in, float* out, hipStream_t s,

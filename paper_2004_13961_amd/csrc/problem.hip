@@ -8,6 +8,7 @@
 //     D[m][k]   = phi_k'(x_m) = -(2k+3) L_{k+1}(x_m)   (derivative relation)
 // applied direction by direction as matrix-core contractions (gemm.hip).
 // W is the tensor Gauss weight, so sum_nodes W g v is exactly (I_N g, v).
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -103,6 +104,7 @@ size_t plan_problem(Problem& P, void* buf) {
     P.s2 = c.take<double>(P.s2n);
     P.s3 = c.take<double>(P.s3n);
     P.flag = c.take<int>(4);
+    P.cmin = c.take<double>(2 * 256 + 2);
     P.bytes = c.off + 256;
     return P.bytes;
 }
@@ -126,9 +128,53 @@ __global__ void node_setup_kernel(int d, int q, int64_t nq, const double* __rest
         wab[nq + idx] = wt * av;
         wab32[idx] = (float)(wt * bv);
         wab32[nq + idx] = (float)(wt * av);
-        // model problem of Sec. 3: a > 0, b >= 0, both finite
-        if (!(av > 0.0) || !(bv >= 0.0) || !isfinite(av) || !isfinite(bv)) atomicOr(flag, 1);
+        // a > 0 and both finite at every node (the bound on b is checked
+        // globally, see coef_min_kernel)
+        if (!(av > 0.0) || !isfinite(av) || !isfinite(bv)) atomicOr(flag, 1);
     }
+}
+
+// The model problem (Sec. 3) asks a >= b1 > 0 and 0 <= b; the paper's own
+// test coefficients (Sec. 5.2, examples with b = cos(x + y)) take b < 0 near
+// a corner. What the method needs is a coercive form: with the Dirichlet
+// Poincare constant of (-1,1)^d, |grad u|^2 >= d pi^2 / 4 |u|^2, the form is
+// positive definite when min b > -(d pi^2 / 4) min a. Per-block minima, then
+// one block compares.
+__global__ void coef_min_kernel(int64_t nq, const double* __restrict__ a, const double* __restrict__ b,
+                                double* __restrict__ part) {
+    __shared__ double sa[256], sb[256];
+    double ma = INFINITY, mb = INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nq; i += (int64_t)gridDim.x * 256) {
+        ma = fmin(ma, a[i]);
+        mb = fmin(mb, b[i]);
+    }
+    sa[threadIdx.x] = ma;
+    sb[threadIdx.x] = mb;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sa[threadIdx.x] = fmin(sa[threadIdx.x], sa[threadIdx.x + o]);
+            sb[threadIdx.x] = fmin(sb[threadIdx.x], sb[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sa[0];
+        part[256 + blockIdx.x] = sb[0];
+    }
+}
+
+__global__ void coef_bound_kernel(int d, int nblocks, double* __restrict__ part, int* flag) {
+    if (threadIdx.x != 0) return;
+    double ma = INFINITY, mb = INFINITY;
+    for (int i = 0; i < nblocks; ++i) {
+        ma = fmin(ma, part[i]);
+        mb = fmin(mb, part[256 + i]);
+    }
+    part[512] = ma;
+    part[513] = mb;
+    const double poincare = d * 2.4674011002723395;   // d * pi^2 / 4
+    if (!(mb > -poincare * ma)) atomicOr(flag, 2);
 }
 
 __global__ void weight_kernel(int64_t nq, const double* __restrict__ W, const double* __restrict__ f,
@@ -219,6 +265,10 @@ lgp_status setup_nodes(Problem& P, const double* a, const double* b, hipStream_t
     LGP_HIP(hipMemcpyAsync(P.s2, P.w.data(), P.q * 8, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(node_setup_kernel, dim3(grid_for(P.nq)), dim3(256), 0, s, P.d, P.q, P.nq,
                        (const double*)P.s2, P.a_nodes, P.b_nodes, P.Wnodes, P.wab, P.wab32, P.flag);
+    const int nb = (int)std::min<int64_t>(256, (P.nq + 255) / 256);
+    hipLaunchKernelGGL(coef_min_kernel, dim3(nb), dim3(256), 0, s, P.nq, (const double*)P.a_nodes,
+                       (const double*)P.b_nodes, P.cmin);
+    hipLaunchKernelGGL(coef_bound_kernel, dim3(1), dim3(64), 0, s, P.d, nb, P.cmin, P.flag);
     LGP_CHECK_LAUNCH();
     int hflag = 0;
     LGP_HIP(hipMemcpyAsync(&hflag, P.flag, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -28,7 +28,7 @@ EXPORTS = [
     "lgp_problem_bytes", "lgp_build_problem", "lgp_destroy_problem", "lgp_load_vector",
     "lgp_matvec", "lgp_factor_bytes", "lgp_factor_M", "lgp_destroy_factor",
     "lgp_precond_apply", "lgp_ilu_forward", "lgp_ilu_backward", "lgp_factor_describe",
-    "lgp_solve_workspace_bytes", "lgp_pcg_solve",
+    "lgp_solve_workspace_bytes", "lgp_pcg_solve", "lgp_factor_const_bytes", "lgp_factor_const",
 ]
 
 
@@ -83,6 +83,8 @@ def lib():
         "lgp_factor_bytes": (sz, [vp, i32, i32, i32]),
         "lgp_factor_M": (i32, [vp, i32, i32, i32, vp, sz, vp, ctypes.POINTER(vp)]),
         "lgp_destroy_factor": (None, [vp]),
+        "lgp_factor_const_bytes": (sz, [vp]),
+        "lgp_factor_const": (i32, [vp, vp, sz, vp, ctypes.POINTER(vp)]),
         "lgp_precond_apply": (i32, [vp, vp, vp, vp]),
         "lgp_ilu_forward": (i32, [vp, vp, vp, vp]),
         "lgp_ilu_backward": (i32, [vp, vp, vp, vp]),

@@ -88,6 +88,24 @@ class Factor:
                              ctypes.byref(h)), "lgp_factor_M")
         self.handle = h
 
+    @classmethod
+    def constant(cls, problem: Problem):
+        """The constant-coefficient preconditioner of PCG-I (a, b replaced by
+        their means), inverted exactly; apply() and pcg_solve() accept it."""
+        L = lib()
+        self = cls.__new__(cls)
+        self.problem = problem
+        self.Ta = self.Tb = 0
+        nbytes = L.lgp_factor_const_bytes(problem.handle)
+        if nbytes == 0:
+            raise lgpcg.LgpError(1, "lgp_factor_const_bytes")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        check(L.lgp_factor_const(problem.handle, _ptr(self.buf), nbytes, _stream(), ctypes.byref(h)),
+              "lgp_factor_const")
+        self.handle = h
+        return self
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value and lgpcg._lib is not None:

@@ -62,3 +62,22 @@ def family_nodal(d: int, N: int, J: int, seed: int, with_rhs: bool = True):
         gdot += da * g1[i] * other
     f = -a * lap - gdot + b * u
     return a, b, f, u
+
+
+def paper_example_nodal(case: str, d: int, N: int):
+    """(a, b, f) at the library nodes for the variable-coefficient examples of
+    the paper's iteration tables (Sec. 5.2; Example 2 in 2D, Example 3 in 3D):
+    case "a": a = (2|x|^2 + 1)^4, b = cos(sum_i x_i); case "b": a =
+    exp(2 sum_i x_i), b = 0. The paper does not state f; f = 1 here."""
+    xs, _ = gauss_legendre(N)
+    X = _axis_coords(xs, d)
+    s = sum(X)
+    if case == "a":
+        a = (2.0 * sum(Xi * Xi for Xi in X) + 1.0) ** 4
+        b = np.cos(s)
+    elif case == "b":
+        a = np.exp(2.0 * s)
+        b = np.zeros((N + 1,) * d)
+    else:
+        raise ValueError(case)
+    return np.ascontiguousarray(a), np.ascontiguousarray(b), np.ones((N + 1,) * d)

@@ -48,5 +48,5 @@ def test_size_queries_and_argument_errors():
     assert L.lgp_factor_bytes(None, 4, 4, 0) == 0
     h = ctypes.c_void_p()
     assert L.lgp_build_problem(4, 10, None, None, None, 0, None, ctypes.byref(h)) == 1
-    assert L.lgp_status_str(3) == b"coefficient violates a > 0, b >= 0 at a node"
+    assert L.lgp_status_str(3) == b"coefficient violates a > 0 at a node, or b below the coercivity bound"
     assert L.lgp_version() >= 100

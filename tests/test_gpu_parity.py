@@ -219,6 +219,11 @@ def test_error_paths():
     with pytest.raises(LgpError) as e:
         Problem(2, N, _dev(bad).reshape(-1), _dev(b).reshape(-1))
     assert e.value.status == 3
+    # b may dip below zero as far as the coercivity bound -(d pi^2/4) min a
+    Problem(2, N, _dev(a).reshape(-1), _dev(np.full_like(b, -0.5)).reshape(-1))
+    with pytest.raises(LgpError) as e:
+        Problem(2, N, _dev(a).reshape(-1), _dev(np.full_like(b, -10.0)).reshape(-1))
+    assert e.value.status == 3
     P = Problem(2, N, _dev(a).reshape(-1), _dev(b).reshape(-1))
     M = Factor(P, 2)
     F = _dev(synth.random_vector((N - 1) ** 2, 3))

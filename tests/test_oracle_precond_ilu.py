@@ -97,6 +97,29 @@ def test_M_row_entries_match_dense(d, N, T):
         assert np.max(np.abs(e - H2[row])) < 1e-13 * np.max(np.abs(M))
 
 
+@pytest.mark.parametrize("d,N", [(2, 9), (2, 14), (3, 6)])
+def test_constant_preconditioner(d, N):
+    """PCG-I's preconditioner (Sec. 5.2): the closed-form Kronecker K0 equals
+    the assembled operator for constant coefficients, and the
+    diagonalisation solve equals a dense solve."""
+    ca, cb = 1.7, 0.4
+    q = N + 1
+    K0 = pc.constant_operator_dense(d, N, ca, cb)
+    Kd = gk.dense_operator(d, N, np.full((q,) * d, ca), np.full((q,) * d, cb))
+    assert np.max(np.abs(K0 - Kd)) < 1e-13 * np.max(np.abs(Kd))
+    r = np.random.default_rng(N).uniform(-1, 1, (N - 1) ** d)
+    z = pc.constant_solve(d, N, ca, cb, r)
+    zd = np.linalg.solve(K0, r)
+    assert np.linalg.norm(z - zd) < 1e-12 * np.linalg.norm(zd)
+    assert np.linalg.norm(pc.constant_apply(d, N, ca, cb, z) - K0 @ z) < 1e-13 * np.linalg.norm(K0 @ z)
+    # the constants of PCG-I are the T = 0 series: the weighted means
+    B, a, b, ah, bh = _config_problem(d, N, 0)
+    ca2, cb2 = pc.constant_coefficients(a, b, B)
+    W = gk.node_weights(B, d)
+    assert abs(ca2 - np.sum(W * a) / 2 ** d) < 1e-14 * abs(ca2)
+    assert abs(cb2 - np.sum(W * b) / 2 ** d) < 1e-14 * abs(cb2)
+
+
 def test_config_pattern_is_box_minus_corners():
     for (d, N, T, J) in [(2, 40, 4, 6), (2, 40, 8, 12), (3, 20, 6, 6)]:
         B, a, b, ah, bh = _config_problem(d, N, T, J=J)
