@@ -101,8 +101,9 @@ size_t lgp_factor_bytes(lgp_problem p, int Ta, int Tb, lgp_dtype store);
 
 /* Preconditioner of Sec. 4.1: a and b replaced by their Legendre series
  * truncated to indices <= Ta (resp. Tb) in each direction (coefficients =
- * the discrete Legendre transform of the nodal values, Sec. 2.2; terms below
- * 1e-13 of the largest are dropped), M assembled exactly (product formula,
+ * the discrete Legendre transform of the nodal values, Sec. 2.2, which
+ * defines degrees <= N only: Ta, Tb above N act as N; terms below 1e-13 of
+ * the largest are dropped), M assembled exactly (product formula,
  * Lemma LegProduct; Kronecker form of Sec. 4.2), then ILU(0) (Alg. 2) in
  * FP64 on the GPU over NZ(M). Because M and NZ(M) are symmetric the factor
  * is stored as unit-lower L plus pivots D, with U = D L^T. Returns

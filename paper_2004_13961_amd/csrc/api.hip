@@ -186,9 +186,11 @@ static void init_factor_dims(Factor& F, const Problem& P, int Ta, int Tb) {
     F.d = P.d;
     F.n1 = P.n1;
     F.n = P.n;
-    F.Ta = Ta;
-    F.Tb = Tb;
-    F.T = std::max(Ta, Tb);
+    // the (N+1)-point transform defines Legendre coefficients of degree <= N
+    // only (Sec. 2.2), so truncations beyond N keep all of them
+    F.Ta = std::min(Ta, P.N);
+    F.Tb = std::min(Tb, P.N);
+    F.T = std::max(F.Ta, F.Tb);
     F.h = F.T + 2;
     F.nlines = (P.d == 2) ? P.n1 : P.n1 * P.n1;
     F.levels = 0;
@@ -288,8 +290,8 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
     double mx = 0.0;
     for (size_t ci = 0; ci < tp; ++ci) {
         const int tx = (int)(ci % T1), ty = (int)((ci / T1) % T1), tz = (d == 3) ? (int)(ci / (T1 * T1)) : 0;
-        if (tx > Ta || ty > Ta || tz > Ta) ca[ci] = 0.0;
-        if (tx > Tb || ty > Tb || tz > Tb) cb[ci] = 0.0;
+        if (tx > F.Ta || ty > F.Ta || tz > F.Ta) ca[ci] = 0.0;
+        if (tx > F.Tb || ty > F.Tb || tz > F.Tb) cb[ci] = 0.0;
         mx = std::max(mx, std::max(std::fabs(ca[ci]), std::fabs(cb[ci])));
     }
     for (size_t ci = 0; ci < tp; ++ci) {

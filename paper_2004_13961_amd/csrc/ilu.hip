@@ -79,7 +79,13 @@ size_t plan_factor(Factor& F, void* buf, bool with32) {
     F.ldl = ((nlo + 1) + 31) & ~31;
     const size_t ldl = (size_t)F.ldl;
     F.L = c.take<double>((size_t)(n + 1) * ldl);
-    F.Ut = c.take<double>((size_t)n * ldl);
+    // Ut doubles as scratch before the transpose: the row order (n ints)
+    // and the folded line coefficients, which on tiny grids outgrow n rows
+    {
+        const int W = 2 * h + 1, nzW = (d == 3) ? W : 1;
+        const size_t scratch = (((size_t)n * 4 + 255) & ~(size_t)255) + (size_t)F.nlines * nzW * W * 2 * (T + 1) * 8;
+        F.Ut = c.take<double>(std::max((size_t)n * ldl, (scratch + 7) / 8));
+    }
     F.Dg = c.take<double>(n);
     F.invD = c.take<double>(n);
     F.has32 = with32;
@@ -1523,11 +1529,7 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
     int* d_order = (int*)F.Ut;
     double* fold = (double*)((char*)F.Ut + (((size_t)n * 4 + 255) & ~(size_t)255));
     const int nzW = (d == 3) ? W : 1;
-    const size_t fold_bytes = (size_t)F.nlines * nzW * W * 2 * T1 * 8;
-    if ((((size_t)n * 4 + 255) & ~(size_t)255) + fold_bytes > (size_t)n * F.ldl * 8) {
-        // small grids: the Ut buffer is too small for the scratch
-        return LGP_E_UNSUPPORTED;
-    }
+    // (plan_factor sized the Ut buffer for this scratch)
     LGP_HIP(hipMemcpyAsync(F.lev, lstart.data(), lstart.size() * 4, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(level_order_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, s,
                        d, n1, n, (int)A1, (int)B1, (const int*)F.lev, F.lev + maxlev + 1, d_order);
