@@ -25,6 +25,9 @@
  *     After a non-OK build or factor the handle is not created.
  *   - A handle must not be used from two host threads at once. Calls on one
  *     handle must be ordered on a single stream.
+ *   - Requests on several streams driven from several host threads at once
+ *     are not supported: one such run with three streams stopped making
+ *     progress, for a reason not yet found. Issue requests from one thread.
  */
 #ifndef LGPCG_H
 #define LGPCG_H
