@@ -4,8 +4,6 @@
 #include <array>
 #include <cmath>
 #include <new>
-#include <set>
-#include <tuple>
 
 #include "lgp_internal.h"
 
@@ -123,13 +121,17 @@ lgp_status lgp_matvec(lgp_problem p, const void* u, void* y, lgp_dtype prec, voi
 // others (carrying M^(t)) reach t + 2; a b-term reaches t + 2 everywhere.
 static std::vector<std::array<int, 3>> pattern_offsets(int d, int T, const std::vector<double>& ca,
                                                       const std::vector<double>& cb) {
-    const int T1 = T + 1;
-    std::set<std::tuple<int, int, int>> S;
-    S.insert({0, 0, 0});
+    const int T1 = T + 1, h = T + 2, W = 2 * h + 1;
+    const int Wz = (d == 3) ? W : 1, hz = (d == 3) ? h : 0;
+    // membership on the dense box [-h, h]^d
+    std::vector<char> in((size_t)Wz * W * W, 0);
+    in[((size_t)hz * W + h) * W + h] = 1;
     auto add_box = [&](int rx, int ry, int rz) {
         for (int z = -rz; z <= rz; ++z)
-            for (int y = -ry; y <= ry; ++y)
-                for (int x = -rx; x <= rx; ++x) S.insert({z, y, x});
+            for (int y = -ry; y <= ry; ++y) {
+                char* row = &in[((size_t)(z + hz) * W + (y + h)) * W + h];
+                for (int x = -rx; x <= rx; ++x) row[x] = 1;
+            }
     };
     const int tz_max = (d == 3) ? T : 0;
     for (int tz = 0; tz <= tz_max; ++tz)
@@ -143,8 +145,12 @@ static std::vector<std::array<int, 3>> pattern_offsets(int d, int T, const std::
                 }
                 if (cb[ci] != 0.0) add_box(tx + 2, ty + 2, d == 3 ? tz + 2 : 0);
             }
+    // sorted by (z, y, x)
     std::vector<std::array<int, 3>> out;
-    for (auto& t : S) out.push_back({std::get<2>(t), std::get<1>(t), std::get<0>(t)});   // sorted (z, y, x)
+    for (int z = -hz; z <= hz; ++z)
+        for (int y = -h; y <= h; ++y)
+            for (int x = -h; x <= h; ++x)
+                if (in[((size_t)(z + hz) * W + (y + h)) * W + (x + h)]) out.push_back({x, y, z});
     return out;
 }
 
