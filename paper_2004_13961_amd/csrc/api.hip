@@ -251,12 +251,14 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
     const size_t need0 = (d == 2) ? (size_t)q * T1 : (size_t)q * q * T1;   // stage outputs
     const size_t need1 = (d == 2) ? 0 : (size_t)q * T1 * T1;
     if (need0 > P.s0n || need1 > P.s1n || (size_t)T1 * q > P.s3n || tp > P.s2n) {
+        factor_release(hF->F);
         delete hF;
         return LGP_E_UNSUPPORTED;
     }
     std::vector<double> ca(tp), cb(tp);
     double* dFT = P.s3;
     if (hipMemcpyAsync(dFT, FT.data(), FT.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
+        factor_release(hF->F);
         delete hF;
         return LGP_E_HIP;
     }
@@ -288,6 +290,7 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
     }
     if (st != LGP_OK) {
         hipStreamSynchronize(s);   // FT must outlive its queued copy
+        factor_release(hF->F);
         delete hF;
         return st;
     }
@@ -306,12 +309,14 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
     }
     set_pattern(F, pattern_offsets(d, T, ca, cb));
     if (plan_factor(F, buf, store != LGP_F64) > buf_bytes) {
+        factor_release(hF->F);
         delete hF;
         return LGP_E_NOMEM;
     }
     if (hipMemcpyAsync(F.coefA, ca.data(), tp * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(F.coefB, cb.data(), tp * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
         hipStreamSynchronize(s);   // ca, cb must outlive their queued copies
+        factor_release(hF->F);
         delete hF;
         return LGP_E_HIP;
     }
@@ -325,6 +330,7 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
             st = LGP_E_ILU_PIVOT;
     }
     if (st != LGP_OK) {
+        factor_release(hF->F);
         delete hF;
         return st;
     }
@@ -332,7 +338,11 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
     return LGP_OK;
 }
 
-void lgp_destroy_factor(lgp_factor m) { delete m; }
+void lgp_destroy_factor(lgp_factor m) {
+    if (!m) return;
+    factor_release(m->F);
+    delete m;
+}
 
 size_t lgp_factor_const_bytes(lgp_problem p) {
     if (!p) return 0;
@@ -348,6 +358,7 @@ lgp_status lgp_factor_const(lgp_problem p, void* buf, size_t buf_bytes, void* st
     if (!hF) return LGP_E_NOMEM;
     lgp_status st = const_factor_build(hF->F, p->P, buf, buf_bytes, (hipStream_t)stream);
     if (st != LGP_OK) {
+        factor_release(hF->F);
         delete hF;
         return st;
     }

@@ -25,6 +25,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "lgp_internal.h"
 
@@ -1363,6 +1365,31 @@ struct FactorHostTables {
 
 static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& H, hipEvent_t* ev);
 
+// One non-blocking stream per device, at the default priority, for work the
+// library overlaps with the caller's stream; created on first use and kept
+// for the life of the process.
+hipStream_t side_stream() {
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[dev] = st;
+    return st;
+}
+
+void factor_release(Factor& F) {
+    if (F.ut_ready) {
+        hipEventSynchronize(F.ut_ready);   // the side stream may still write Ut
+        hipEventDestroy(F.ut_ready);
+        F.ut_ready = nullptr;
+    }
+}
+
 lgp_status factor_build(Factor& F, hipStream_t s) {
     FactorHostTables H;
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1603,29 +1630,46 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
     F.nruns = (int)runs.size() / 4;
     int R = 256;
     while (R > 16 && (size_t)(R + maxspan) * maxK * 8 > 64 * 1024) R /= 2;
-    if (F.nruns > 0 && (size_t)(R + maxspan) * maxK * 8 <= 64 * 1024) {
-        LGP_HIP(hipMemcpyAsync(F.runs, runs.data(), runs.size() * 4, hipMemcpyHostToDevice, s));
+    const bool tiled = F.nruns > 0 && (size_t)(R + maxspan) * maxK * 8 <= 64 * 1024;
+    if (tiled) LGP_HIP(hipMemcpyAsync(F.runs, runs.data(), runs.size() * 4, hipMemcpyHostToDevice, s));
+    // after 1/D at n_lower, rows of L end in zeros; the forward sweep needs L only
+    if (F.ldl > F.nlo + 1)
+        hipLaunchKernelGGL(zero_pad_kernel, dim3(4096), dim3(256), 0, s, n, F.ldl, F.nlo + 1, F.L);
+    if (F.has32) {
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.ldl, (const double*)F.L, F.L32);
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n, (const double*)F.invD, F.invD32);
+    }
+    LGP_CHECK_LAUNCH();
+    // The backward operator Ut is built on the library's side stream, after
+    // everything above: a solve's first forward substitution (which leaves
+    // most of the GPU idle) overlaps it, and backward substitutions wait for
+    // F.ut_ready. Reads of L (entries < n_lower) do not meet the padding
+    // writes above.
+    hipStream_t side = side_stream();
+    if (!side) return LGP_E_HIP;
+    if (!F.ut_ready) LGP_HIP(hipEventCreateWithFlags(&F.ut_ready, hipEventDisableTiming));
+    hipEvent_t e0 = nullptr;
+    LGP_HIP(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
+    LGP_HIP(hipEventRecord(e0, s));
+    const hipError_t werr = hipStreamWaitEvent(side, e0, 0);
+    hipEventDestroy(e0);
+    if (werr != hipSuccess) return LGP_E_HIP;
+    if (tiled) {
         const size_t shmem = (size_t)(R + maxspan) * maxK * 8;
         hipFuncSetAttribute((const void*)build_ut_tiled_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)shmem);
-        hipLaunchKernelGGL(build_ut_tiled_kernel, dim3((unsigned)((n + R - 1) / R), F.nruns), dim3(256), shmem, s, d,
-                           n1, n, F.ldl, (const int4*)F.d_offs, (const int4*)F.runs, R, (const double*)F.L, F.Ut);
+        hipLaunchKernelGGL(build_ut_tiled_kernel, dim3((unsigned)((n + R - 1) / R), F.nruns), dim3(256), shmem, side,
+                           d, n1, n, F.ldl, (const int4*)F.d_offs, (const int4*)F.runs, R, (const double*)F.L, F.Ut);
     } else {
-        hipLaunchKernelGGL(build_ut_kernel, dim3(4096), dim3(256), 0, s, d, n1, n, F.nlo, F.ldl,
+        hipLaunchKernelGGL(build_ut_kernel, dim3(4096), dim3(256), 0, side, d, n1, n, F.nlo, F.ldl,
                            (const int4*)F.d_offs, (const double*)F.L, F.Ut);
     }
+    hipLaunchKernelGGL(zero_pad_kernel, dim3(4096), dim3(256), 0, side, n, F.ldl, F.nlo, F.Ut);
+    if (F.has32)
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, side, (int64_t)n * F.ldl, (const double*)F.Ut,
+                           F.Ut32);
     LGP_CHECK_LAUNCH();
-    // after 1/D at n_lower, rows of L and Ut end in zeros
-    if (F.ldl > F.nlo + 1)
-        hipLaunchKernelGGL(zero_pad_kernel, dim3(4096), dim3(256), 0, s, n, F.ldl, F.nlo + 1, F.L);
-    hipLaunchKernelGGL(zero_pad_kernel, dim3(4096), dim3(256), 0, s, n, F.ldl, F.nlo, F.Ut);
-    LGP_CHECK_LAUNCH();
-    if (F.has32) {
-        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.ldl, (const double*)F.L, F.L32);
-        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.ldl, (const double*)F.Ut, F.Ut32);
-        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n, (const double*)F.invD, F.invD32);
-        LGP_CHECK_LAUNCH();
-    }
+    LGP_HIP(hipEventRecord(F.ut_ready, side));
     return LGP_OK;
 }
 
@@ -1703,12 +1747,14 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
 }
 
 lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStream_t s, const int* stop) {
+    if (backward && F.ut_ready) LGP_HIP(hipStreamWaitEvent(s, F.ut_ready, 0));
     return backward ? sweep_t<double>(F, true, F.Ut, F.invD, in, out, s, stop)
                     : sweep_t<double>(F, false, F.L, nullptr, in, out, s, stop);
 }
 
 lgp_status sweep32(Factor& F, bool backward, const float* in, float* out, hipStream_t s, const int* stop) {
     if (!F.has32) return LGP_E_ARG;
+    if (backward && F.ut_ready) LGP_HIP(hipStreamWaitEvent(s, F.ut_ready, 0));
     return backward ? sweep_t<float>(F, true, F.Ut32, F.invD32, in, out, s, stop)
                     : sweep_t<float>(F, false, F.L32, nullptr, in, out, s, stop);
 }

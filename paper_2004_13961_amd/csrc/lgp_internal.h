@@ -130,6 +130,7 @@ struct Factor {
     // kind 1: the constant-coefficient operator solved exactly (matrix
     // diagonalisation); only P, d, n1, n and the cc* fields are used
     int kind = 0;
+    hipEvent_t ut_ready = nullptr;   // Ut (and its FP32 copy) complete on the library's side stream
     double* ccE = nullptr;     // [n1][n1] generalized eigenvectors, E^T S E = I, E^T M E = diag(lam)
     double* ccLam = nullptr;   // [n1]
     double* ccInv = nullptr;   // [n1^d] 1 / eigenvalues of the transformed operator
@@ -143,6 +144,8 @@ struct Factor {
 
 size_t plan_factor(Factor& F, void* buf, bool with32);
 lgp_status factor_build(Factor& F, hipStream_t s);
+hipStream_t side_stream();
+void factor_release(Factor& F);
 size_t const_factor_bytes(const Problem& P);
 lgp_status const_factor_build(Factor& F, Problem& P, void* buf, size_t bytes, hipStream_t s);
 lgp_status const_apply(Factor& F, const double* r, double* z, hipStream_t s);
