@@ -136,8 +136,8 @@ def main():
                          "for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this solver runs each request on a single GPU "
-              "and multi-GPU runs are not part of this build (requested --gpus %d)" % args.gpus)
+        print("bench.py measures one GPU only: the solver runs each request on a single GPU "
+              "and has no multi-GPU path (requested --gpus %d)" % args.gpus)
         sys.exit(2)
 
     import torch

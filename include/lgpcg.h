@@ -48,7 +48,7 @@ typedef enum {
     LGP_E_NOCONV = 5,     /* max_iter reached before the stop rule of Alg. 1 */
     LGP_E_BREAKDOWN = 6,  /* p'Kp <= 0 or r'z <= 0 in PCG */
     LGP_E_HIP = 7,        /* a HIP runtime call failed; see lgp_last_hip_error */
-    LGP_E_UNSUPPORTED = 8 /* valid request this build does not serve */
+    LGP_E_UNSUPPORTED = 8 /* valid request the library does not serve */
 } lgp_status;
 
 typedef enum { LGP_F64 = 0, LGP_F32 = 1, LGP_BF16 = 2 } lgp_dtype;

@@ -227,23 +227,38 @@ __global__ void tables_kernel(int N, const double* __restrict__ xn, double* __re
         // here l0 = L_k, l1 = L_{k+1}, l2 = L_{k+2}
         const double phi = l0 - l2;
         const double dphi = -(2.0 * k + 3.0) * l1;
+        // node-major layouts: consecutive threads write consecutive nodes
         PDT[(size_t)k * 2 * q + m] = phi;
         PDT[(size_t)k * 2 * q + q + m] = dphi;
-        PhiD[(size_t)m * n1 + k] = phi;
-        PhiD[(size_t)(q + m) * n1 + k] = dphi;
-        DP[(size_t)m * n1 + k] = dphi;
-        DP[(size_t)(q + m) * n1 + k] = phi;
         PDT32[(size_t)k * 2 * q + m] = (float)phi;
         PDT32[(size_t)k * 2 * q + q + m] = (float)dphi;
-        PhiD32[(size_t)m * n1 + k] = (float)phi;
-        PhiD32[(size_t)(q + m) * n1 + k] = (float)dphi;
-        DP32[(size_t)m * n1 + k] = (float)dphi;
-        DP32[(size_t)(q + m) * n1 + k] = (float)phi;
         const int j = k + 2;   // L_{j+1} = ((2j+1) z L_j - j L_{j-1}) / (j+1)
         const double l3 = ((2.0 * j + 1.0) * z * l2 - j * l1) / (j + 1.0);
         l0 = l1;
         l1 = l2;
         l2 = l3;
+    }
+}
+
+// the basis-major layouts [Phi; D] and [D; Phi], copied from PDT so that
+// consecutive threads write consecutive basis indices
+__global__ void tables_transpose_kernel(int N, const double* __restrict__ PDT, double* __restrict__ PhiD,
+                                        double* __restrict__ DP, float* __restrict__ PhiD32,
+                                        float* __restrict__ DP32) {
+    const int q = N + 1, n1 = N - 1;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)q * n1;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int m = (int)(e / n1), k = (int)(e % n1);
+        const double phi = PDT[(size_t)k * 2 * q + m];
+        const double dphi = PDT[(size_t)k * 2 * q + q + m];
+        PhiD[(size_t)m * n1 + k] = phi;
+        PhiD[(size_t)(q + m) * n1 + k] = dphi;
+        DP[(size_t)m * n1 + k] = dphi;
+        DP[(size_t)(q + m) * n1 + k] = phi;
+        PhiD32[(size_t)m * n1 + k] = (float)phi;
+        PhiD32[(size_t)(q + m) * n1 + k] = (float)dphi;
+        DP32[(size_t)m * n1 + k] = (float)dphi;
+        DP32[(size_t)(q + m) * n1 + k] = (float)phi;
     }
 }
 
@@ -253,6 +268,9 @@ lgp_status build_tables(Problem& P, hipStream_t s) {
     LGP_HIP(hipMemcpyAsync(P.s3, P.x.data(), P.q * 8, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(tables_kernel, dim3((P.q + 127) / 128), dim3(128), 0, s, P.N, (const double*)P.s3, P.PDT,
                        P.PhiD, P.DP, P.PDT32, P.PhiD32, P.DP32);
+    const int64_t nt = (int64_t)P.q * P.n1;
+    hipLaunchKernelGGL(tables_transpose_kernel, dim3((unsigned)std::min<int64_t>(4096, (nt + 255) / 256)), dim3(256), 0,
+                       s, P.N, (const double*)P.PDT, P.PhiD, P.DP, P.PhiD32, P.DP32);
     LGP_CHECK_LAUNCH();
     return LGP_OK;
 }
