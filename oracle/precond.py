@@ -278,7 +278,7 @@ def stencil_rows(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray, offsets,
                  S=None, Mm=None) -> np.ndarray:
     """H[row, o] = M(row, row + offsets[o]) for every row, from the Kronecker
     form (each term separable, so each offset is a tensor product of 1D
-    diagonals contracted with the coefficient array). d = 2, 3."""
+    diagonals contracted with the coefficient array). d = 1, 2, 3."""
     Ta = ahat.shape[0] - 1
     Tb = bhat.shape[0] - 1
     T = max(Ta, Tb)
@@ -302,7 +302,10 @@ def stencil_rows(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray, offsets,
             tmp = np.tensordot(tmp, Fy, axes=(0, 0))             # [t, z, y]
             return np.tensordot(tmp, Fx, axes=(0, 0))            # [z, y, x]
 
-        if d == 2:
+        if d == 1:
+            # sum_t a_t S^(t) + b_t M^(t) along the one direction
+            val = np.tensordot(A, Sd[0], axes=(0, 0)) + np.tensordot(Bc, Md[0], axes=(0, 0))
+        elif d == 2:
             # coefficient index [s (y), t (x)]
             val = term(A, None, Md[1], Sd[0]) + term(A, None, Sd[1], Md[0]) + term(Bc, None, Md[1], Md[0])
         else:

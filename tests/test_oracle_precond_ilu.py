@@ -68,7 +68,7 @@ def _config_problem(d, N, T, J=6, seed=0):
     return B, a, b, ah, bh
 
 
-@pytest.mark.parametrize("d,N,T", [(2, 12, 4), (2, 20, 8), (3, 6, 2)])
+@pytest.mark.parametrize("d,N,T", [(1, 30, 4), (1, 12, 8), (2, 12, 4), (2, 20, 8), (3, 6, 2)])
 def test_M_spd_symmetric_and_pattern(d, N, T):
     B, a, b, ah, bh = _config_problem(d, N, T)
     M = pc.dense_M(d, N - 1, ah, bh)
