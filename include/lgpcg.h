@@ -1,6 +1,7 @@
 /* lgpcg.h - C ABI of the MI355X (gfx950) preconditioned Legendre-Galerkin
  * PCG solver for  -div(a grad u) + b u = f  on (-1,1)^d, u = 0 on the
- * boundary, d = 2 or 3 (Diao, Hu, Ma, arXiv 2004.13961).
+ * boundary, d = 1, 2 or 3 (Diao, Hu, Ma, arXiv 2004.13961; d = 1 is the
+ * setting of the paper's Example 1, solved by the same entry points).
  *
  * Discretisation (paper Sec. 3): unknowns are the coefficients of the compact
  * basis phi_k = L_k - L_{k+2}, k = 0..N-2, in tensor form, x index fastest:
@@ -67,7 +68,8 @@ int lgp_last_hip_error(void);            /* last hipError_t seen, 0 if none */
 lgp_status lgp_gauss_legendre(int N, double* x, double* w);
 
 /* ------------------------------------------------------------ problem -- */
-/* Device bytes needed by lgp_build_problem for (d, N). */
+/* Device bytes needed by lgp_build_problem for (d, N); 0 if (d, N) is out
+ * of range (d in 1..3, 2 <= N <= 4096, or N <= 65536 for d = 1). */
 size_t lgp_problem_bytes(int d, int N);
 
 /* Build the operator K = A + B of Sec. 3 / Sec. 4.3 from nodal coefficient
@@ -109,7 +111,9 @@ size_t lgp_factor_bytes(lgp_problem p, int Ta, int Tb, lgp_dtype store);
  * the largest are dropped), M assembled exactly (product formula,
  * Lemma LegProduct; Kronecker form of Sec. 4.2), then ILU(0) (Alg. 2) in
  * FP64 on the GPU over NZ(M). Because M and NZ(M) are symmetric the factor
- * is stored as unit-lower L plus pivots D, with U = D L^T. Returns
+ * is stored as unit-lower L plus pivots D, with U = D L^T. For d = 1, M is
+ * banded and NZ(M) is its whole band, so ILU(0) is the exact banded
+ * factorisation, and the substitutions are sequential over the rows. Returns
  * LGP_E_ILU_PIVOT if a pivot is <= 0 or non-finite. Synchronises `stream`
  * (pattern selection and the pivot check read device results). */
 lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store,
@@ -129,7 +133,11 @@ void lgp_destroy_factor(lgp_factor m);
  * inner = LGP_F64 (PCG-I); lgp_ilu_forward, lgp_ilu_backward and
  * lgp_factor_describe return LGP_E_UNSUPPORTED for it, and so does
  * lgp_pcg_solve with a low-precision inner solve. Buffer: device bytes from
- * lgp_factor_const_bytes, owned by the caller. Synchronises `stream`. */
+ * lgp_factor_const_bytes, owned by the caller. Synchronises `stream`.
+ * For d = 1, K0 = c_a S + c_b M is banded and equals the T = 0 truncation
+ * of lgp_factor_M, so this call returns lgp_factor_M(p, 0, 0, LGP_F64, ...):
+ * an exact banded factorisation, an ordinary ILU(0) handle (all of the
+ * entry points above accept it). */
 size_t lgp_factor_const_bytes(lgp_problem p);
 lgp_status lgp_factor_const(lgp_problem p, void* buf, size_t buf_bytes, void* stream, lgp_factor* out);
 

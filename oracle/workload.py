@@ -78,7 +78,7 @@ def rhs_f(c: np.ndarray, xs) -> np.ndarray:
 
 def paper_example(case: str, d: int, xs):
     """(a, b) of the paper's variable-coefficient examples (Sec. 5.2):
-    Example 2 (d = 2) and Example 3 (d = 3); case "a": a = (2|x|^2 + 1)^4,
+    Example 1 (d = 1), 2 (d = 2) and 3 (d = 3); case "a": a = (2|x|^2 + 1)^4,
     b = cos(sum_i x_i); case "b": a = exp(2 sum_i x_i), b = 0."""
     X = _grid(xs, d)
     s = sum(X)

@@ -48,7 +48,7 @@ lgp_status lgp_gauss_legendre(int N, double* x, double* w) {
     return LGP_OK;
 }
 
-static bool valid_dims(int d, int N) { return (d == 2 || d == 3) && N >= 2 && N <= 4096; }
+static bool valid_dims(int d, int N) { return d >= 1 && d <= 3 && N >= 2 && N <= (d == 1 ? 65536 : 4096); }
 
 static void init_problem_dims(Problem& P, int d, int N) {
     P.d = d;
@@ -133,9 +133,16 @@ static std::vector<std::array<int, 3>> pattern_offsets(int d, int T, const std::
                 for (int x = -rx; x <= rx; ++x) row[x] = 1;
             }
     };
-    const int tz_max = (d == 3) ? T : 0;
+    if (d == 1) {
+        // one direction: an a-term carries S^(t) (reach t), a b-term M^(t)
+        for (int t = 0; t <= T; ++t) {
+            if (ca[t] != 0.0) add_box(t, 0, 0);
+            if (cb[t] != 0.0) add_box(t + 2, 0, 0);
+        }
+    }
+    const int tz_max = (d == 3) ? T : 0, ty_max = (d == 1) ? -1 : T;
     for (int tz = 0; tz <= tz_max; ++tz)
-        for (int ty = 0; ty <= T; ++ty)
+        for (int ty = 0; ty <= ty_max; ++ty)
             for (int tx = 0; tx <= T; ++tx) {
                 const size_t ci = ((size_t)tz * T1 + ty) * T1 + tx;
                 if (ca[ci] != 0.0) {
@@ -198,7 +205,7 @@ static void init_factor_dims(Factor& F, const Problem& P, int Ta, int Tb) {
     F.Tb = std::min(Tb, P.N);
     F.T = std::max(F.Ta, F.Tb);
     F.h = F.T + 2;
-    F.nlines = (P.d == 2) ? P.n1 : P.n1 * P.n1;
+    F.nlines = (P.d == 1) ? 1 : (P.d == 2) ? P.n1 : P.n1 * P.n1;
     F.levels = 0;
 }
 
@@ -208,7 +215,8 @@ size_t lgp_factor_bytes(lgp_problem p, int Ta, int Tb, lgp_dtype store) {
     init_factor_dims(F, p->P, Ta, Tb);
     // upper bound: the full box |delta_k| <= h
     const int T1 = F.T + 1;
-    const size_t tp = (p->P.d == 2) ? (size_t)T1 * T1 : (size_t)T1 * T1 * T1;
+    size_t tp = 1;
+    for (int k = 0; k < p->P.d; ++k) tp *= (size_t)T1;
     std::vector<double> ones(tp, 1.0);
     set_pattern(F, pattern_offsets(p->P.d, F.T, ones, ones));
     return plan_factor(F, nullptr, store != LGP_F64);
@@ -227,7 +235,8 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
     Factor& F = hF->F;
     init_factor_dims(F, P, Ta, Tb);
     const int T = F.T, T1 = T + 1, q = P.q, d = P.d;
-    const size_t tp = (d == 2) ? (size_t)T1 * T1 : (size_t)T1 * T1 * T1;
+    size_t tp = 1;
+    for (int k = 0; k < d; ++k) tp *= (size_t)T1;
     lgp_status st = LGP_OK;
     // --- truncated Legendre coefficients: FDLT of the nodal values (Sec. 2.2),
     //     indices <= T per direction, as contractions with
@@ -248,8 +257,8 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
             FT[(size_t)t * q + m] = (2 * t + 1) / 2.0 * P.w[m] * lt;
         }
     }
-    const size_t need0 = (d == 2) ? (size_t)q * T1 : (size_t)q * q * T1;   // stage outputs
-    const size_t need1 = (d == 2) ? 0 : (size_t)q * T1 * T1;
+    const size_t need0 = (d == 1) ? 0 : (d == 2) ? (size_t)q * T1 : (size_t)q * q * T1;   // stage outputs
+    const size_t need1 = (d == 3) ? (size_t)q * T1 * T1 : 0;
     if (need0 > P.s0n || need1 > P.s1n || (size_t)T1 * q > P.s3n || tp > P.s2n) {
         factor_release(hF->F);
         delete hF;
@@ -265,7 +274,11 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
     for (int which = 0; which < 2 && st == LGP_OK; ++which) {
         const double* src = which == 0 ? P.a_nodes : P.b_nodes;
         double* dst = P.s2;   // (T+1)^d result
-        if (d == 2) {
+        if (d == 1) {
+            // C (T1) = FT f
+            GemmArgs g1 = {dFT, 0, q, 1, src, 0, 1, 1, dst, 0, 1, 1, nullptr, 0, 0, 0, T1, 1, q, 1, 0};
+            st = gemm(GEMM_F64, g1, s);
+        } else if (d == 2) {
             // X (q x T1) = f (q x q) FT^T ; C (T1 x T1) = FT X
             GemmArgs g1 = {src, 0, q, 1, dFT, 0, 1, q, P.s0, 0, T1, 1, nullptr, 0, 0, 0, q, T1, q, 1, 0};
             GemmArgs g2 = {dFT, 0, q, 1, P.s0, 0, T1, 1, dst, 0, T1, 1, nullptr, 0, 0, 0, T1, T1, q, 1, 0};
@@ -344,8 +357,13 @@ void lgp_destroy_factor(lgp_factor m) {
     delete m;
 }
 
+// In one dimension K0 = c_a S + c_b M is banded (half-width 2) and equals
+// the T = 0 truncation (a^_0, b^_0 are the means of a and b), whose ILU(0)
+// on the full band is its exact LDL^T factorisation: O(N) work, where the
+// diagonalisation would need a dense eigenbasis.
 size_t lgp_factor_const_bytes(lgp_problem p) {
     if (!p) return 0;
+    if (p->P.d == 1) return lgp_factor_bytes(p, 0, 0, LGP_F64);
     return const_factor_bytes(p->P);
 }
 
@@ -354,6 +372,7 @@ lgp_status lgp_factor_const(lgp_problem p, void* buf, size_t buf_bytes, void* st
     *out = nullptr;
     if (!p || !buf) return LGP_E_ARG;
     if (buf_bytes < lgp_factor_const_bytes(p)) return LGP_E_NOMEM;
+    if (p->P.d == 1) return lgp_factor_M(p, 0, 0, LGP_F64, buf, buf_bytes, stream, out);
     lgp_factor_s* hF = new (std::nothrow) lgp_factor_s();
     if (!hF) return LGP_E_NOMEM;
     lgp_status st = const_factor_build(hF->F, p->P, buf, buf_bytes, (hipStream_t)stream);

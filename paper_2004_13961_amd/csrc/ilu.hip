@@ -1343,6 +1343,167 @@ __global__ __launch_bounds__(768) void ilu_factor2_kernel(
     }
 }
 
+// ------------------------------------------------------- d = 1 --------
+// In one dimension M is banded (half-width h = T + 2) and NZ(M) is the whole
+// band, so ILU(0) is the exact banded factorisation M = L D L^T: rows in
+// order, one wavefront, lane m holding lower offset m. The left-looking
+// recurrence of the 2D/3D kernels (u_j = M(i,j) - sum_k u_k L(j,k),
+// L(i,j) = u_j / D(j), D(i) = M(i,i) - sum_j u_j L(i,j)) is evaluated with
+// the previous h rows kept in LDS.
+__global__ __launch_bounds__(64) void band1d_factor_kernel(int n1, int nlo, int ldl, int T, int h,
+                                                           const int4* __restrict__ offs,
+                                                           const double* __restrict__ band,
+                                                           const double* __restrict__ ca,
+                                                           const double* __restrict__ cb, double* __restrict__ L,
+                                                           double* __restrict__ Dg, double* __restrict__ invD,
+                                                           int* flag) {
+    __shared__ double ring[64][65];   // rows i-1 .. i-64 (by i mod 64): L entries, then 1/D at nlo
+    __shared__ double uu[64];
+    const int lane = threadIdx.x;
+    const int W = 2 * h + 1, T1 = T + 1;
+    const int64_t bandT = (int64_t)n1 * W;
+    const int dl = lane < nlo ? offs[lane].x : 0;   // this lane's lower offset (negative)
+    auto Mentry = [&](int i, int dx) {
+        double v = 0.0;
+        for (int t = 0; t < T1; ++t) {
+            const int64_t e = t * bandT + (int64_t)i * W + (dx + h);
+            v += ca[t] * band[e] + cb[t] * band[e + (int64_t)T1 * bandT];
+        }
+        return v;
+    };
+    for (int i = 0; i < n1; ++i) {
+        // M(i, i + offset_lane) and M(i, i)
+        const bool inl = lane < nlo && i + dl >= 0;
+        const double mrow = inl ? Mentry(i, dl) : 0.0;
+        const double mii = Mentry(i, 0);
+        double piv = 0.0;
+        for (int jl = 0; jl < nlo; ++jl) {
+            const int dj = offs[jl].x;
+            const int j = i + dj;
+            // u_j = M(i,j) - sum over earlier offsets m of u_m L(j, j + (d_m - d_j))
+            double acc = 0.0;
+            if (lane < jl && j >= 0) {
+                const int dk = dl - dj;          // < 0: offset from row j
+                const int sk = dk + nlo;         // its slot (lower offsets are -nlo .. -1)
+                if (i + dl >= 0 && sk >= 0) acc = uu[lane] * ring[j & 63][sk];
+            }
+            acc = wave_sum(acc);
+            const double mj = __shfl(mrow, jl, 64);
+            const double uj = (j >= 0) ? mj - acc : 0.0;
+            if (lane == jl) uu[jl] = uj;
+            const double dinv = (j >= 0) ? ring[j & 63][nlo] : 0.0;
+            piv += (lane == jl) ? uj * uj * dinv : 0.0;
+            __syncthreads();   // uu[jl] visible to the next offsets
+        }
+        piv = wave_sum(piv);
+        const double Dii = mii - piv;
+        const double iv = 1.0 / Dii;
+        double* Li = L + (int64_t)i * ldl;
+        if (lane < nlo) {
+            const int j = i + dl;
+            const double lij = (j >= 0) ? uu[lane] * ring[j & 63][nlo] : 0.0;
+            Li[lane] = lij;
+            ring[i & 63][lane] = lij;
+        }
+        if (lane == 0) {
+            Li[nlo] = iv;
+            ring[i & 63][nlo] = iv;
+            Dg[i] = Dii;
+            invD[i] = iv;
+            if (!(Dii > 0.0) || !isfinite(Dii)) atomicOr(flag, 1);
+        }
+        for (int k = nlo + 1 + lane; k < ldl; k += 64) Li[k] = 0.0;
+        __syncthreads();
+    }
+}
+
+// Substitutions on the band, one wavefront, rows in order (forward) or in
+// reverse order (backward, U = D L^T: z_i = y_i / D_i - sum_k L(i - d_k, k)
+// z(i - d_k)); the last 64 results stay in LDS.
+template <typename T, bool REV>
+__global__ __launch_bounds__(64) void band1d_sweep_kernel(int n1, int nlo, int ldl, const int4* __restrict__ offs,
+                                                          const T* __restrict__ A, const T* __restrict__ invd,
+                                                          const T* __restrict__ in, T* __restrict__ out) {
+    __shared__ T win[64];
+    const int lane = threadIdx.x;
+    const int dl = lane < nlo ? offs[lane].x : 0;
+    win[lane] = T(0);
+    __syncthreads();
+    // this lane's coefficient and the right-hand side of row i: independent
+    // of the recurrence, so row i+1's are loaded while row i is reduced
+    auto coef = [&](int i) -> T {
+        const int src = REV ? i - dl : i + dl;
+        if (lane >= nlo || src < 0 || src >= n1) return T(0);
+        return REV ? A[(int64_t)src * ldl + lane] : A[(int64_t)i * ldl + lane];
+    };
+    auto rhs = [&](int i) -> T { return REV ? in[i] * invd[i] : in[i]; };
+    int i = REV ? n1 - 1 : 0;
+    T a = coef(i), r = rhs(i);
+    for (int s = 0; s < n1; ++s) {
+        const int inext = REV ? i - 1 : i + 1;
+        T an = T(0), rn = T(0);
+        if (s + 1 < n1) {
+            an = coef(inext);
+            rn = rhs(inext);
+        }
+        const int src = REV ? i - dl : i + dl;
+        const T acc = wave_sum(lane < nlo && src >= 0 && src < n1 ? a * win[src & 63] : T(0));
+        const T y = r - acc;
+        __syncthreads();
+        if (lane == 0) {
+            win[i & 63] = y;
+            out[i] = y;
+        }
+        __syncthreads();
+        a = an;
+        r = rn;
+        i = inext;
+    }
+}
+
+static lgp_status band1d_build(Factor& F, std::vector<int>& off4, hipStream_t s) {
+    const int n1 = F.n1, T = F.T, h = F.h;
+    const int64_t n = F.n;
+    if (F.nlo > 63 || F.ldl > 4096) return LGP_E_UNSUPPORTED;
+    {
+        const int64_t total = (int64_t)(T + 1) * n1 * (2 * h + 1);
+        hipLaunchKernelGGL(band_kernel, dim3((unsigned)std::min<int64_t>(4096, (total + 255) / 256)), dim3(256), 0,
+                           s, T, n1, h, F.band);
+    }
+    off4.assign((size_t)4 * (F.nlo + 1), 0);
+    for (int k = 0; k <= F.nlo; ++k) {
+        off4[4 * k + 0] = F.offs[3 * k];
+        off4[4 * k + 3] = F.offs[3 * k];
+    }
+    LGP_HIP(hipMemcpyAsync(F.d_offs, off4.data(), off4.size() * 4, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemsetAsync(F.flag, 0, 16, s));
+    LGP_HIP(hipMemsetAsync(F.L + (size_t)n * F.ldl, 0, (size_t)F.ldl * 8, s));   // zero row
+    hipLaunchKernelGGL(band1d_factor_kernel, dim3(1), dim3(64), 0, s, n1, F.nlo, F.ldl, T, h,
+                       (const int4*)F.d_offs, (const double*)F.band, (const double*)F.coefA,
+                       (const double*)F.coefB, F.L, F.Dg, F.invD, F.flag);
+    if (F.has32) {
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.ldl, (const double*)F.L, F.L32);
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n, (const double*)F.invD, F.invD32);
+    }
+    LGP_CHECK_LAUNCH();
+    F.factor_kernel = 1;
+    F.levels = n1;
+    return LGP_OK;
+}
+
+template <typename T>
+static lgp_status band1d_sweep(Factor& F, bool backward, const T* A, const T* invd, const T* in, T* out,
+                               hipStream_t s) {
+    if (backward)
+        hipLaunchKernelGGL((band1d_sweep_kernel<T, true>), dim3(1), dim3(64), 0, s, F.n1, F.nlo, F.ldl,
+                           (const int4*)F.d_offs, A, invd, in, out);
+    else
+        hipLaunchKernelGGL((band1d_sweep_kernel<T, false>), dim3(1), dim3(64), 0, s, F.n1, F.nlo, F.ldl,
+                           (const int4*)F.d_offs, A, invd, in, out);
+    LGP_CHECK_LAUNCH();
+    return LGP_OK;
+}
+
 // ------------------------------------------------------------- host ------
 static int persistent_grid(const void* kernel, int block, size_t shmem, int64_t units) {
     int dev = 0, cus = 256, per = 1;
@@ -1408,6 +1569,12 @@ lgp_status factor_build(Factor& F, hipStream_t s) {
 }
 
 static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& H, hipEvent_t* ev) {
+    if (F.d == 1) {
+        if (ev) hipEventRecord(ev[0], s);
+        const lgp_status st1 = band1d_build(F, H.off4, s);
+        if (ev) hipEventRecord(ev[1], s);
+        return st1;
+    }
     const int d = F.d, n1 = F.n1, T = F.T, h = F.h;
     const int W = 2 * h + 1, T1 = T + 1;
     const int64_t n = F.n;
@@ -1747,6 +1914,7 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
 }
 
 lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStream_t s, const int* stop) {
+    if (F.d == 1) return band1d_sweep<double>(F, backward, F.L, F.invD, in, out, s);
     if (backward && F.ut_ready) LGP_HIP(hipStreamWaitEvent(s, F.ut_ready, 0));
     return backward ? sweep_t<double>(F, true, F.Ut, F.invD, in, out, s, stop)
                     : sweep_t<double>(F, false, F.L, nullptr, in, out, s, stop);
@@ -1754,6 +1922,7 @@ lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStr
 
 lgp_status sweep32(Factor& F, bool backward, const float* in, float* out, hipStream_t s, const int* stop) {
     if (!F.has32) return LGP_E_ARG;
+    if (F.d == 1) return band1d_sweep<float>(F, backward, F.L32, F.invD32, in, out, s);
     if (backward && F.ut_ready) LGP_HIP(hipStreamWaitEvent(s, F.ut_ready, 0));
     return backward ? sweep_t<float>(F, true, F.Ut32, F.invD32, in, out, s, stop)
                     : sweep_t<float>(F, false, F.L32, nullptr, in, out, s, stop);

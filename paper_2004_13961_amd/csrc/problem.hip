@@ -75,7 +75,12 @@ size_t plan_problem(Problem& P, void* buf) {
     P.PhiD32 = c.take<float>(tab);
     P.DP32 = c.take<float>(tab);
     P.wab32 = c.take<float>(2 * P.nq);
-    if (P.d == 2) {
+    if (P.d == 1) {
+        P.s0n = (size_t)2 * q;
+        P.s1n = (size_t)2 * q;
+        P.s2n = (size_t)2 * q;
+        P.s3n = (size_t)2 * q;
+    } else if (P.d == 2) {
         P.s0n = (size_t)n1 * 2 * q;
         P.s1n = (size_t)2 * q * q;
         P.s2n = (size_t)q * q;
@@ -91,9 +96,9 @@ size_t plan_problem(Problem& P, void* buf) {
     {
         const size_t T1 = 25;
         const size_t q_ = (size_t)q;
-        const size_t st0 = (P.d == 2) ? q_ * T1 : q_ * q_ * T1;
-        const size_t st1 = (P.d == 2) ? 0 : q_ * T1 * T1;
-        const size_t st2 = (P.d == 2) ? T1 * T1 : T1 * T1 * T1;
+        const size_t st0 = (P.d == 1) ? 0 : (P.d == 2) ? q_ * T1 : q_ * q_ * T1;
+        const size_t st1 = (P.d == 3) ? q_ * T1 * T1 : 0;
+        const size_t st2 = (P.d == 1) ? T1 : (P.d == 2) ? T1 * T1 : T1 * T1 * T1;
         if (P.s0n < st0) P.s0n = st0;
         if (P.s1n < st1) P.s1n = st1;
         if (P.s2n < st2) P.s2n = st2;
@@ -314,6 +319,13 @@ static lgp_status matvec_impl(Problem& P, const T* u, T* y, GemmMode mode, const
     } while (0)
     // GemmArgs field order:
     // A,sAb,sAi,sAk, B,sBb,sBk,sBj, C,sCb,sCi,sCj, E,sEb,sEi,sEj, M,N,K,batch, accumulate
+    if (P.d == 1) {
+        // [g0; g1] = ([Phi; D] u) .* [Wb; Wa]               (2q)
+        GEMM({PhiD, 0, n1, 1, u, 0, 1, 1, s1, 0, 1, 1, wab, 0, 1, 1, 2 * q, 1, n1, 1, 0});
+        // y = Phi^T g0 + D^T g1                             (n1)
+        GEMM({PDT, 0, 2 * q, 1, s1, 0, 1, 1, y, 0, 1, 1, nullptr, 0, 0, 0, n1, 1, 2 * q, 1, 0});
+        return LGP_OK;
+    }
     if (P.d == 2) {
         // stage 1: T = U [Phi^T | D^T]                 (n1 x 2q)
         GEMM({u, 0, n1, 1, PDT, 0, 2 * q, 1, s0, 0, 2 * q, 1, nullptr, 0, 0, 0, n1, 2 * q, n1, 1, 0});
@@ -380,6 +392,11 @@ lgp_status load_vector(Problem& P, const double* f, double* F, hipStream_t s) {
         GemmArgs g_ = __VA_ARGS__;                                  \
         if ((st = gemm(GEMM_F64, g_, s)) != LGP_OK) return st;      \
     } while (0)
+    if (P.d == 1) {
+        // F = Phi^T g                                       (n1)
+        GEMM({P.PDT, 0, 2 * q, 1, P.s2, 0, 1, 1, F, 0, 1, 1, nullptr, 0, 0, 0, n1, 1, q, 1, 0});
+        return LGP_OK;
+    }
     if (P.d == 2) {
         // A = Phi^T g (n1 x q), F = A Phi (n1 x n1)
         GEMM({P.PDT, 0, 2 * q, 1, P.s2, 0, q, 1, P.s3, 0, q, 1, nullptr, 0, 0, 0, n1, q, q, 1, 0});

@@ -66,7 +66,7 @@ def family_nodal(d: int, N: int, J: int, seed: int, with_rhs: bool = True):
 
 def paper_example_nodal(case: str, d: int, N: int):
     """(a, b, f) at the library nodes for the variable-coefficient examples of
-    the paper's iteration tables (Sec. 5.2; Example 2 in 2D, Example 3 in 3D):
+    the paper's iteration tables (Sec. 5.2; Examples 1, 2, 3 in 1D, 2D, 3D):
     case "a": a = (2|x|^2 + 1)^4, b = cos(sum_i x_i); case "b": a =
     exp(2 sum_i x_i), b = 0. The paper does not state f; f = 1 here."""
     xs, _ = gauss_legendre(N)

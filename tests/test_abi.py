@@ -43,8 +43,13 @@ def test_size_queries_and_argument_errors():
     L = lgpcg.lib()
     assert L.lgp_problem_bytes(2, 32) > 0
     assert L.lgp_problem_bytes(3, 16) > 0
-    assert L.lgp_problem_bytes(1, 32) == 0
+    assert L.lgp_problem_bytes(1, 32) > 0
+    assert L.lgp_problem_bytes(1, 10240) > 0
+    assert L.lgp_problem_bytes(0, 32) == 0
+    assert L.lgp_problem_bytes(4, 8) == 0
     assert L.lgp_problem_bytes(2, 1) == 0
+    assert L.lgp_problem_bytes(2, 4097) == 0
+    assert L.lgp_problem_bytes(1, 65537) == 0
     assert L.lgp_factor_bytes(None, 4, 4, 0) == 0
     h = ctypes.c_void_p()
     assert L.lgp_build_problem(4, 10, None, None, None, 0, None, ctypes.byref(h)) == 1

@@ -232,3 +232,26 @@ def test_paper_iteration_counts_soft(golden_dir):
     mv = lambda v: gk.matvec_sumfact(2, N, a, b, v, B)
     x, k, _ = opcg.pcg(mv, st.apply, F, 1e-12)
     assert 3 <= k <= 20
+
+
+def test_1d_constant_preconditioner_is_t0_band_factor():
+    """In 1D, K0 = c_a S + c_b M (Sec. 5.2) is banded and equals the T = 0
+    truncation (the degree-0 Legendre coefficient is the mean), and ILU(0)
+    on its full band is exact: the stencil ILU and the diagonalisation solve
+    are two independent routes to the same K0^{-1} r."""
+    N = 90
+    B = gk.Basis(N)
+    rng = np.random.default_rng(5)
+    a = 1.0 + rng.random(N + 1)
+    b = rng.random(N + 1)
+    ca, cb = pc.constant_coefficients(a, b, B)
+    ah, bh = pc.series_pair(a, b, B, 0, 0)
+    assert abs(ah[0] - ca) <= 1e-14 * ca and abs(bh[0] - cb) <= 1e-14 * cb
+    offs = pc.stencil_offsets(ah, bh)
+    assert offs == [(-2,), (-1,), (0,), (1,), (2,)]
+    st = ilu.StencilILU(1, N - 1, offs, pc.stencil_rows(1, N - 1, ah, bh, offs)).factor()
+    r = rng.standard_normal(N - 1)
+    z1 = st.apply(r)
+    z2 = pc.constant_solve(1, N, ca, cb, r)
+    assert np.linalg.norm(z1 - z2) <= 1e-11 * np.linalg.norm(z2)
+    assert np.linalg.norm(pc.constant_apply(1, N, ca, cb, z1) - r) <= 1e-12 * np.linalg.norm(r)
