@@ -13,6 +13,11 @@ direction this is exactly (N+1)-point Gauss quadrature of the bilinear form
 Array conventions: a coefficient vector of length (N-1)^d is reshaped to
 (n1,)*d with x on the LAST axis; node arrays are (q,)*d with x last.
 
+The diffusion coefficient is either one field a (the isotropic problem of
+Sec. 3) or a list of d fields [a_1, ..., a_d] (a_1 for x), the diagonal
+anisotropic form -sum_j (a_j u_{x_j})_{x_j} + b u of Example 4 (Sec. 5.2);
+the bilinear form then weights the j-th gradient component by a_j.
+
 Three independent routes to K u are given:
   dense_operator          K assembled entry by entry from node sums (tiny N)
   matvec_sumfact          one 1D table per direction applied along each axis
@@ -61,6 +66,15 @@ def node_weights(basis: Basis, d: int) -> np.ndarray:
     return W
 
 
+def a_by_direction(a_nodes, d: int):
+    """[a_1, ..., a_d] (direction 0 = x): the list itself for the anisotropic
+    form, d references to the one field otherwise."""
+    if isinstance(a_nodes, (list, tuple)):
+        assert len(a_nodes) == d
+        return [np.asarray(a, dtype=np.float64) for a in a_nodes]
+    return [np.asarray(a_nodes, dtype=np.float64)] * d
+
+
 def dense_operator(d: int, N: int, a_nodes, b_nodes) -> np.ndarray:
     """K_ij = sum_nodes W [a grad psi_i . grad psi_j + b psi_i psi_j]  (G-NI).
 
@@ -69,7 +83,7 @@ def dense_operator(d: int, N: int, a_nodes, b_nodes) -> np.ndarray:
     that direction's Phi for D. For tiny N only (dense n x n)."""
     B = Basis(N)
     W = node_weights(B, d).reshape(-1)
-    a = np.asarray(a_nodes, dtype=np.float64).reshape(-1) * W
+    a_dir = [a.reshape(-1) * W for a in a_by_direction(a_nodes, d)]
     b = np.asarray(b_nodes, dtype=np.float64).reshape(-1) * W
     Psi = _kron_all([B.Phi] * d)
     K = Psi.T @ (b[:, None] * Psi)
@@ -77,7 +91,7 @@ def dense_operator(d: int, N: int, a_nodes, b_nodes) -> np.ndarray:
         mats = [B.Phi] * d
         mats[d - 1 - i] = B.D
         G = _kron_all(mats)
-        K += G.T @ (a[:, None] * G)
+        K += G.T @ (a_dir[i][:, None] * G)
     return K
 
 
@@ -89,7 +103,7 @@ def matvec_sumfact(d: int, N: int, a_nodes, b_nodes, u, basis: Basis = None):
     n1 = B.n1
     U = np.asarray(u, dtype=np.float64).reshape((n1,) * d)
     W = node_weights(B, d)
-    wa = W * np.asarray(a_nodes).reshape((B.q,) * d)
+    wa = [W * a.reshape((B.q,) * d) for a in a_by_direction(a_nodes, d)]
     wb = W * np.asarray(b_nodes).reshape((B.q,) * d)
 
     def fwd(deriv_axis):
@@ -111,7 +125,7 @@ def matvec_sumfact(d: int, N: int, a_nodes, b_nodes, u, basis: Basis = None):
 
     y = bwd(wb * fwd(None), None)
     for i in range(d):
-        y = y + bwd(wa * fwd(i), i)
+        y = y + bwd(wa[i] * fwd(i), i)
     return y.reshape(-1)
 
 
@@ -139,7 +153,7 @@ def matvec_sumfact_ext(d: int, N: int, a_nodes, b_nodes, u, basis: Basis = None)
     for _ in range(d - 1):
         W = np.multiply.outer(w, W)
     U = np.asarray(u, dtype=np.float64).astype(LD).reshape((B.n1,) * d)
-    wa = W * np.asarray(a_nodes, dtype=np.float64).astype(LD).reshape((B.q,) * d)
+    wa = [W * a.astype(LD).reshape((B.q,) * d) for a in a_by_direction(a_nodes, d)]
     wb = W * np.asarray(b_nodes, dtype=np.float64).astype(LD).reshape((B.q,) * d)
 
     def along(T, arr, ax):
@@ -159,7 +173,7 @@ def matvec_sumfact_ext(d: int, N: int, a_nodes, b_nodes, u, basis: Basis = None)
 
     y = bwd(wb * fwd(None), None)
     for i in range(d):
-        y = y + bwd(wa * fwd(i), i)
+        y = y + bwd(wa[i] * fwd(i), i)
     return y.reshape(-1).astype(np.float64)
 
 

@@ -17,6 +17,11 @@ Readings of the paper used here (where it is silent):
     whose series coefficient is not negligible (|c| > 1e-13 * max|c|):
     per direction S^(t) reaches |delta| <= t and M^(t) reaches |delta| <= t+2.
     Entries inside that union are kept even when they happen to be zero.
+
+The anisotropic form of Example 4 (Sec. 5.2) has one diffusion field per
+direction: there `ahat` is a list [a_1 series, ..., a_d series], each with
+its own truncation t_{1j}, and the term with S^(t) in direction j carries
+the series of a_j. A single array means the same series in every direction.
 """
 from __future__ import annotations
 
@@ -39,6 +44,22 @@ def truncated_coefficients(nodal: np.ndarray, basis: Basis, T: int) -> np.ndarra
     c = lg.tensor_fdlt(np.asarray(nodal, dtype=np.float64), basis.PN, basis.w)
     sl = tuple(slice(0, T + 1) for _ in range(c.ndim))
     return c[sl].copy()
+
+
+def _a_list(ahat, d: int):
+    return list(ahat) if isinstance(ahat, (list, tuple)) else [ahat] * d
+
+
+def series_dir(a_dir, b_nodes, basis: Basis, Ta_dir, Tb: int):
+    """Anisotropic form: ([a_1 series <= Ta_dir[0]], ..., b series <= Tb),
+    with the same negligible-term rule as series_pair over all d+1 series."""
+    ahs = [truncated_coefficients(a, basis, t) for a, t in zip(a_dir, Ta_dir)]
+    bh = truncated_coefficients(b_nodes, basis, Tb)
+    mx = max(max(np.max(np.abs(ah)) for ah in ahs), np.max(np.abs(bh)))
+    for ah in ahs:
+        ah[np.abs(ah) <= NEGLIGIBLE * mx] = 0.0
+    bh[np.abs(bh) <= NEGLIGIBLE * mx] = 0.0
+    return ahs, bh
 
 
 def series_pair(a_nodes, b_nodes, basis: Basis, Ta: int, Tb: int):
@@ -141,7 +162,8 @@ def stencil_offsets(ahat: np.ndarray, bhat: np.ndarray):
     the others (carrying M^(t)) reach |d| <= t+2; a b-term reaches t+2 in all
     directions. Returned sorted in column order (lexicographic on
     (dz, dy, dx)), which equals column order for every in-grid pair."""
-    d = ahat.ndim
+    d = bhat.ndim if bhat is not None else _a_list(ahat, 1)[0].ndim
+    a_dir = _a_list(ahat, d)
     offs = set([tuple([0] * d)])
 
     def add_box(reach):
@@ -149,9 +171,9 @@ def stencil_offsets(ahat: np.ndarray, bhat: np.ndarray):
         for pt in np.ndindex(*[len(r) for r in rng]):
             offs.add(tuple(rng[k][pt[k]] for k in range(d)))
 
-    for idx in _support(ahat):
-        deg = idx[::-1]                    # (t_x, t_y, ...)
-        for s_dir in range(d):
+    for s_dir in range(d):                 # the direction carrying S^(t)
+        for idx in _support(a_dir[s_dir]):
+            deg = idx[::-1]                # (t_x, t_y, ...)
             reach = [deg[k] + 2 for k in range(d)]
             reach[s_dir] = deg[s_dir]
             add_box(reach)
@@ -174,16 +196,19 @@ def dense_M(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray) -> np.ndarray:
     """M = sum_t a_t [sum over directions of (S^(t_dir) in that direction,
     M^(t) in the others)] + sum_t b_t (M^(t) in all directions), as the
     Kronecker sum of Sec. 4.2 (kron order z, y, x). Dense; tiny n only."""
-    T = max(ahat.shape[0], bhat.shape[0] if bhat is not None else 0) - 1
+    a_dir = _a_list(ahat, d)
+    T = max(max(ah.shape[0] for ah in a_dir), bhat.shape[0] if bhat is not None else 0) - 1
     S, Mm = band_factors(n1, T)
     n = n1 ** d
     M = np.zeros((n, n))
-    for idx in np.ndindex(*ahat.shape):
-        c = ahat[idx]
-        if c == 0.0:
-            continue
-        # idx = (t_z, t_y, t_x) ~ kron factor order
-        for s_pos in range(d):
+    for s_pos in range(d):
+        # kron position s_pos (order z, y, x) is direction d-1-s_pos
+        ah = a_dir[d - 1 - s_pos]
+        for idx in np.ndindex(*ah.shape):
+            c = ah[idx]
+            if c == 0.0:
+                continue
+            # idx = (t_z, t_y, t_x) ~ kron factor order
             mats = [S[idx[k]] if k == s_pos else Mm[idx[k]] for k in range(d)]
             M += c * _kron_all(mats)
     if bhat is not None:
@@ -279,15 +304,18 @@ def stencil_rows(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray, offsets,
     """H[row, o] = M(row, row + offsets[o]) for every row, from the Kronecker
     form (each term separable, so each offset is a tensor product of 1D
     diagonals contracted with the coefficient array). d = 1, 2, 3."""
-    Ta = ahat.shape[0] - 1
+    a_dir = _a_list(ahat, d)
     Tb = bhat.shape[0] - 1
-    T = max(Ta, Tb)
+    T = max(max(ah.shape[0] - 1 for ah in a_dir), Tb)
     if S is None:
         S, Mm = band_factors(n1, T)
     n = n1 ** d
     H = np.zeros((n, len(offsets)))
-    A = np.zeros((T + 1,) * d)
-    A[tuple(slice(0, Ta + 1) for _ in range(d))] = ahat
+    Ad = []                                # per direction, padded to T
+    for ah in a_dir:
+        A = np.zeros((T + 1,) * d)
+        A[tuple(slice(0, ah.shape[0]) for _ in range(d))] = ah
+        Ad.append(A)
     Bc = np.zeros((T + 1,) * d)
     Bc[tuple(slice(0, Tb + 1) for _ in range(d))] = bhat
     for o, off in enumerate(offsets):
@@ -304,13 +332,14 @@ def stencil_rows(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray, offsets,
 
         if d == 1:
             # sum_t a_t S^(t) + b_t M^(t) along the one direction
-            val = np.tensordot(A, Sd[0], axes=(0, 0)) + np.tensordot(Bc, Md[0], axes=(0, 0))
+            val = np.tensordot(Ad[0], Sd[0], axes=(0, 0)) + np.tensordot(Bc, Md[0], axes=(0, 0))
         elif d == 2:
-            # coefficient index [s (y), t (x)]
-            val = term(A, None, Md[1], Sd[0]) + term(A, None, Sd[1], Md[0]) + term(Bc, None, Md[1], Md[0])
+            # coefficient index [s (y), t (x)]; S in x carries a_1, S in y a_2
+            val = (term(Ad[0], None, Md[1], Sd[0]) + term(Ad[1], None, Sd[1], Md[0])
+                   + term(Bc, None, Md[1], Md[0]))
         else:
-            val = (term(A, Md[2], Md[1], Sd[0]) + term(A, Md[2], Sd[1], Md[0])
-                   + term(A, Sd[2], Md[1], Md[0]) + term(Bc, Md[2], Md[1], Md[0]))
+            val = (term(Ad[0], Md[2], Md[1], Sd[0]) + term(Ad[1], Md[2], Sd[1], Md[0])
+                   + term(Ad[2], Sd[2], Md[1], Md[0]) + term(Bc, Md[2], Md[1], Md[0]))
         H[:, o] = val.reshape(-1)
     return H
 
@@ -319,6 +348,10 @@ def stencil_rows(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray, offsets,
 def constant_coefficients(a_nodes, b_nodes, basis: Basis):
     """(c_a, c_b): the series of a and b truncated at T = 0 (Sec. 4.1), the
     preconditioner of the comparison method PCG-I (Sec. 5.2)."""
+    if isinstance(a_nodes, (list, tuple)):
+        # anisotropic form: one constant per direction
+        ahs, bh = series_dir(a_nodes, b_nodes, basis, [0] * len(a_nodes), 0)
+        return [float(ah.reshape(-1)[0]) for ah in ahs], float(bh.reshape(-1)[0])
     ah, bh = series_pair(a_nodes, b_nodes, basis, 0, 0)
     return float(ah.reshape(-1)[0]), float(bh.reshape(-1)[0])
 
@@ -328,11 +361,12 @@ def constant_operator_dense(d: int, N: int, ca: float, cb: float) -> np.ndarray:
     from the closed-form 1D stiffness and mass of the compact basis."""
     from .galerkin import constant_coefficient_factors
     S1, M1 = constant_coefficient_factors(N)
+    cs = _a_list(ca, d)
     K = cb * _kron_all([M1] * d)
     for i in range(d):
         mats = [M1] * d
-        mats[i] = S1
-        K = K + ca * _kron_all(mats)
+        mats[i] = S1                       # kron position i = direction d-1-i
+        K = K + cs[d - 1 - i] * _kron_all(mats)
     return K
 
 
@@ -353,14 +387,15 @@ def constant_solve(d: int, N: int, ca: float, cb: float, r) -> np.ndarray:
     prod = np.ones_like(grids[0])
     for g in grids:
         prod = prod * g
-    pair = np.zeros_like(grids[0])
-    for i in range(d):
+    cs = _a_list(ca, d)
+    den = cb * prod
+    for i in range(d):                     # S along axis i = direction d-1-i
         term = np.ones_like(grids[0])
         for k in range(d):
             if k != i:
                 term = term * grids[k]
-        pair = pair + term
-    V = V / (ca * pair + cb * prod)
+        den = den + cs[d - 1 - i] * term
+    V = V / den
     for ax in range(d):
         V = lg.apply_along(E, V, ax)
     return V.reshape(-1)
@@ -379,9 +414,10 @@ def constant_apply(d: int, N: int, ca: float, cb: float, z) -> np.ndarray:
             out = lg.apply_along(mats[ax], out, ax)
         return out
 
+    cs = _a_list(ca, d)
     y = cb * chain([M1] * d)
     for i in range(d):
         mats = [M1] * d
-        mats[i] = S1
-        y = y + ca * chain(mats)
+        mats[i] = S1                       # axis i = direction d-1-i
+        y = y + cs[d - 1 - i] * chain(mats)
     return y.reshape(-1)

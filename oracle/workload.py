@@ -91,3 +91,11 @@ def paper_example(case: str, d: int, xs):
     else:
         raise ValueError(case)
     return a, b
+
+
+def example4(d: int, xs):
+    """(a_dir, b) of the anisotropic Example 4 (Sec. 5.2): a_1 = exp(2x),
+    a_2 = cos(y), a_3 = cos(z) (d = 3), b = 0; each field on the full grid."""
+    X = _grid(xs, d)
+    a_dir = [np.exp(2.0 * X[0])] + [np.cos(X[j]) for j in range(1, d)]
+    return a_dir, np.zeros_like(X[0])
