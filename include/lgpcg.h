@@ -84,6 +84,17 @@ size_t lgp_problem_bytes(int d, int N);
  * scratch and must outlive the handle. */
 lgp_status lgp_build_problem(int d, int N, const double* a_nodes, const double* b_nodes,
                              void* buf, size_t buf_bytes, void* stream, lgp_problem* out);
+
+/* The diagonal anisotropic form of Example 4 (Sec. 5.2):
+ *   -sum_j (a_j u_{x_j})_{x_j} + b u = f,  one diffusion field per direction.
+ * a_dir (device, d * (N+1)^d doubles) holds a_1 (the x field), then a_2,
+ * then a_3, each on the full node grid, x fastest (Example 4's a_j depend on
+ * x_j only, but any positive fields are accepted). The bilinear form weights
+ * the j-th gradient component by I_N a_j. Checks, errors, buffer (same size
+ * as lgp_problem_bytes(d, N)) and ownership as lgp_build_problem; every
+ * other entry point accepts the handle. For d = 1 it is lgp_build_problem. */
+lgp_status lgp_build_problem_diag(int d, int N, const double* a_dir, const double* b_nodes,
+                                  void* buf, size_t buf_bytes, void* stream, lgp_problem* out);
 void lgp_destroy_problem(lgp_problem p);
 
 /* Load vector F_k = (I_N f, psi_k) (Sec. 3 with the quadrature of Sec. 4.3):
@@ -118,12 +129,24 @@ size_t lgp_factor_bytes(lgp_problem p, int Ta, int Tb, lgp_dtype store);
  * (pattern selection and the pivot check read device results). */
 lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store,
                         void* buf, size_t buf_bytes, void* stream, lgp_factor* out);
+
+/* Per-direction truncations t_{1j} (Example 4, Sec. 5.2): Ta_dir (host, d
+ * ints, each 0..24) truncates the series of a_j (or of the one field a of
+ * an isotropic problem in the terms where direction j carries S^(t)) at
+ * indices <= Ta_dir[j] per direction; Tb as above. lgp_factor_M(p, Ta, Tb,
+ * ...) is this call with Ta_dir = {Ta, Ta, Ta}. Returns LGP_E_ARG for a
+ * truncation outside 0..24, otherwise as lgp_factor_M. */
+size_t lgp_factor_bytes_dir(lgp_problem p, const int* Ta_dir, int Tb, lgp_dtype store);
+lgp_status lgp_factor_M_dir(lgp_problem p, const int* Ta_dir, int Tb, lgp_dtype store,
+                            void* buf, size_t buf_bytes, void* stream, lgp_factor* out);
 void lgp_destroy_factor(lgp_factor m);
 
 /* The constant-coefficient preconditioner of the comparison method PCG-I
  * (Sec. 5.2): a and b replaced by their series truncated at T = 0 (their
  * weighted means c_a, c_b, Sec. 4.1), i.e.
  *   K0 = c_a (S (x) M + M (x) S) + c_b M (x) M      (2D; three terms in 3D)
+ * (for the anisotropic form, c_a (S (x) M) becomes c_{a_1} M (x) S and
+ * c_{a_2} S (x) M, kron order y, x: one mean per field)
  * with the exact 1D stiffness S = diag(4k+6) and the pentadiagonal 1D mass M
  * of the compact basis (Sec. 2.1, 3). The paper solves K0 by a fast direct
  * method; here it is inverted exactly by matrix diagonalisation (generalized

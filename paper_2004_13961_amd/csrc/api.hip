@@ -70,8 +70,8 @@ size_t lgp_problem_bytes(int d, int N) {
     return plan_problem(P, nullptr);
 }
 
-lgp_status lgp_build_problem(int d, int N, const double* a_nodes, const double* b_nodes, void* buf,
-                             size_t buf_bytes, void* stream, lgp_problem* out) {
+static lgp_status build_problem(int d, int N, const double* a_nodes, const double* b_nodes, bool aniso, void* buf,
+                                size_t buf_bytes, void* stream, lgp_problem* out) {
     if (!out) return LGP_E_ARG;
     *out = nullptr;
     if (!valid_dims(d, N) || !a_nodes || !b_nodes || !buf) return LGP_E_ARG;
@@ -79,6 +79,7 @@ lgp_status lgp_build_problem(int d, int N, const double* a_nodes, const double* 
     if (!h) return LGP_E_NOMEM;
     Problem& P = h->P;
     init_problem_dims(P, d, N);
+    P.aniso = aniso;
     if (plan_problem(P, buf) > buf_bytes) {
         delete h;
         return LGP_E_NOMEM;
@@ -94,6 +95,16 @@ lgp_status lgp_build_problem(int d, int N, const double* a_nodes, const double* 
     }
     *out = h;
     return LGP_OK;
+}
+
+lgp_status lgp_build_problem(int d, int N, const double* a_nodes, const double* b_nodes, void* buf,
+                             size_t buf_bytes, void* stream, lgp_problem* out) {
+    return build_problem(d, N, a_nodes, b_nodes, false, buf, buf_bytes, stream, out);
+}
+
+lgp_status lgp_build_problem_diag(int d, int N, const double* a_dir, const double* b_nodes, void* buf,
+                                  size_t buf_bytes, void* stream, lgp_problem* out) {
+    return build_problem(d, N, a_dir, b_nodes, true, buf, buf_bytes, stream, out);
 }
 
 void lgp_destroy_problem(lgp_problem p) { delete p; }
@@ -119,6 +130,8 @@ lgp_status lgp_matvec(lgp_problem p, const void* u, void* y, lgp_dtype prec, voi
 // boxes each Kronecker term can reach: for an a-term with degrees
 // (tx, ty, tz) the direction carrying S^(t) reaches |delta| <= t and the
 // others (carrying M^(t)) reach t + 2; a b-term reaches t + 2 everywhere.
+// ca holds d series of (T+1)^d coefficients, direction j (x first) at j*(T+1)^d:
+// the term with S^(t) in direction j carries a_j's series.
 static std::vector<std::array<int, 3>> pattern_offsets(int d, int T, const std::vector<double>& ca,
                                                       const std::vector<double>& cb) {
     const int T1 = T + 1, h = T + 2, W = 2 * h + 1;
@@ -133,10 +146,15 @@ static std::vector<std::array<int, 3>> pattern_offsets(int d, int T, const std::
                 for (int x = -rx; x <= rx; ++x) row[x] = 1;
             }
     };
+    size_t tp = 1;
+    for (int k = 0; k < d; ++k) tp *= (size_t)T1;
+    const double* cax = ca.data();
+    const double* cay = (d >= 2) ? ca.data() + tp : nullptr;
+    const double* caz = (d == 3) ? ca.data() + 2 * tp : nullptr;
     if (d == 1) {
         // one direction: an a-term carries S^(t) (reach t), a b-term M^(t)
         for (int t = 0; t <= T; ++t) {
-            if (ca[t] != 0.0) add_box(t, 0, 0);
+            if (cax[t] != 0.0) add_box(t, 0, 0);
             if (cb[t] != 0.0) add_box(t + 2, 0, 0);
         }
     }
@@ -145,11 +163,9 @@ static std::vector<std::array<int, 3>> pattern_offsets(int d, int T, const std::
         for (int ty = 0; ty <= ty_max; ++ty)
             for (int tx = 0; tx <= T; ++tx) {
                 const size_t ci = ((size_t)tz * T1 + ty) * T1 + tx;
-                if (ca[ci] != 0.0) {
-                    add_box(tx, ty + 2, d == 3 ? tz + 2 : 0);
-                    add_box(tx + 2, ty, d == 3 ? tz + 2 : 0);
-                    if (d == 3) add_box(tx + 2, ty + 2, tz);
-                }
+                if (cax[ci] != 0.0) add_box(tx, ty + 2, d == 3 ? tz + 2 : 0);
+                if (cay[ci] != 0.0) add_box(tx + 2, ty, d == 3 ? tz + 2 : 0);
+                if (d == 3 && caz[ci] != 0.0) add_box(tx + 2, ty + 2, tz);
                 if (cb[ci] != 0.0) add_box(tx + 2, ty + 2, d == 3 ? tz + 2 : 0);
             }
     // sorted by (z, y, x)
@@ -194,14 +210,18 @@ static void set_pattern(Factor& F, const std::vector<std::array<int, 3>>& offs) 
     F.npairs = count_pairs(lower, F.h);
 }
 
-static void init_factor_dims(Factor& F, const Problem& P, int Ta, int Tb) {
+static void init_factor_dims(Factor& F, const Problem& P, const int* Tdir, int Tb) {
     F.P = const_cast<Problem*>(&P);
     F.d = P.d;
     F.n1 = P.n1;
     F.n = P.n;
     // the (N+1)-point transform defines Legendre coefficients of degree <= N
     // only (Sec. 2.2), so truncations beyond N keep all of them
-    F.Ta = std::min(Ta, P.N);
+    F.Ta = 0;
+    for (int j = 0; j < 3; ++j) {
+        F.Tdir[j] = (j < P.d) ? std::min(Tdir[j], P.N) : 0;
+        F.Ta = std::max(F.Ta, F.Tdir[j]);
+    }
     F.Tb = std::min(Tb, P.N);
     F.T = std::max(F.Ta, F.Tb);
     F.h = F.T + 2;
@@ -209,31 +229,43 @@ static void init_factor_dims(Factor& F, const Problem& P, int Ta, int Tb) {
     F.levels = 0;
 }
 
-size_t lgp_factor_bytes(lgp_problem p, int Ta, int Tb, lgp_dtype store) {
-    if (!p || Ta < 0 || Tb < 0) return 0;
+static bool valid_truncations(const Problem& P, const int* Tdir, int Tb) {
+    if (!Tdir || Tb < 0 || Tb > 24) return false;
+    for (int j = 0; j < P.d; ++j)
+        if (Tdir[j] < 0 || Tdir[j] > 24) return false;
+    return true;
+}
+
+size_t lgp_factor_bytes_dir(lgp_problem p, const int* Ta_dir, int Tb, lgp_dtype store) {
+    if (!p || !valid_truncations(p->P, Ta_dir, Tb)) return 0;
     Factor F;
-    init_factor_dims(F, p->P, Ta, Tb);
+    init_factor_dims(F, p->P, Ta_dir, Tb);
     // upper bound: the full box |delta_k| <= h
     const int T1 = F.T + 1;
     size_t tp = 1;
     for (int k = 0; k < p->P.d; ++k) tp *= (size_t)T1;
-    std::vector<double> ones(tp, 1.0);
-    set_pattern(F, pattern_offsets(p->P.d, F.T, ones, ones));
+    std::vector<double> ones(tp, 1.0), ones_a((size_t)p->P.d * tp, 1.0);
+    set_pattern(F, pattern_offsets(p->P.d, F.T, ones_a, ones));
     return plan_factor(F, nullptr, store != LGP_F64);
 }
 
-lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* buf, size_t buf_bytes, void* stream,
-                        lgp_factor* out) {
+size_t lgp_factor_bytes(lgp_problem p, int Ta, int Tb, lgp_dtype store) {
+    const int Tdir[3] = {Ta, Ta, Ta};
+    return lgp_factor_bytes_dir(p, Tdir, Tb, store);
+}
+
+lgp_status lgp_factor_M_dir(lgp_problem p, const int* Ta_dir, int Tb, lgp_dtype store, void* buf, size_t buf_bytes,
+                            void* stream, lgp_factor* out) {
     if (!out) return LGP_E_ARG;
     *out = nullptr;
-    if (!p || !buf || Ta < 0 || Tb < 0 || Ta > 24 || Tb > 24) return LGP_E_ARG;
-    if (buf_bytes < lgp_factor_bytes(p, Ta, Tb, store)) return LGP_E_NOMEM;
+    if (!p || !buf || !valid_truncations(p->P, Ta_dir, Tb)) return LGP_E_ARG;
+    if (buf_bytes < lgp_factor_bytes_dir(p, Ta_dir, Tb, store)) return LGP_E_NOMEM;
     Problem& P = p->P;
     hipStream_t s = (hipStream_t)stream;
     lgp_factor_s* hF = new (std::nothrow) lgp_factor_s();
     if (!hF) return LGP_E_NOMEM;
     Factor& F = hF->F;
-    init_factor_dims(F, P, Ta, Tb);
+    init_factor_dims(F, P, Ta_dir, Tb);
     const int T = F.T, T1 = T + 1, q = P.q, d = P.d;
     size_t tp = 1;
     for (int k = 0; k < d; ++k) tp *= (size_t)T1;
@@ -264,15 +296,17 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
         delete hF;
         return LGP_E_UNSUPPORTED;
     }
-    std::vector<double> ca(tp), cb(tp);
+    // one series per stored diffusion field, then b's
+    const int nfa = P.aniso ? d : 1;
+    std::vector<double> cf((size_t)nfa * tp), cb(tp);
     double* dFT = P.s3;
     if (hipMemcpyAsync(dFT, FT.data(), FT.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
         factor_release(hF->F);
         delete hF;
         return LGP_E_HIP;
     }
-    for (int which = 0; which < 2 && st == LGP_OK; ++which) {
-        const double* src = which == 0 ? P.a_nodes : P.b_nodes;
+    for (int which = 0; which <= nfa && st == LGP_OK; ++which) {
+        const double* src = which < nfa ? P.a_nodes + (size_t)which * P.nq : P.b_nodes;
         double* dst = P.s2;   // (T+1)^d result
         if (d == 1) {
             // C (T1) = FT f
@@ -295,8 +329,8 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
                 st = gemm(GEMM_F64, g3, s);
         }
         if (st == LGP_OK) {
-            std::vector<double>& h = which == 0 ? ca : cb;
-            if (hipMemcpyAsync(h.data(), dst, tp * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            double* h = which < nfa ? cf.data() + (size_t)which * tp : cb.data();
+            if (hipMemcpyAsync(h, dst, tp * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 st = LGP_E_HIP;
         }
@@ -307,26 +341,37 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
         delete hF;
         return st;
     }
-    // keep indices <= Ta (a) and <= Tb (b); drop terms below 1e-13 of the
-    // largest magnitude over both series
+    // the series of a_j (direction j, x first) kept for indices <= T_j, b's
+    // for indices <= Tb; terms below 1e-13 of the largest magnitude over all
+    // the series dropped
+    std::vector<double> ca((size_t)d * tp);
     double mx = 0.0;
+    for (int j = 0; j < d; ++j) {
+        const double* fj = cf.data() + (size_t)(P.aniso ? j : 0) * tp;
+        const int Tj = F.Tdir[j];
+        for (size_t ci = 0; ci < tp; ++ci) {
+            const int tx = (int)(ci % T1), ty = (int)((ci / T1) % T1), tz = (d == 3) ? (int)(ci / (T1 * T1)) : 0;
+            const bool keep = tx <= Tj && ty <= Tj && tz <= Tj;
+            ca[(size_t)j * tp + ci] = keep ? fj[ci] : 0.0;
+            mx = std::max(mx, std::fabs(ca[(size_t)j * tp + ci]));
+        }
+    }
     for (size_t ci = 0; ci < tp; ++ci) {
         const int tx = (int)(ci % T1), ty = (int)((ci / T1) % T1), tz = (d == 3) ? (int)(ci / (T1 * T1)) : 0;
-        if (tx > F.Ta || ty > F.Ta || tz > F.Ta) ca[ci] = 0.0;
         if (tx > F.Tb || ty > F.Tb || tz > F.Tb) cb[ci] = 0.0;
-        mx = std::max(mx, std::max(std::fabs(ca[ci]), std::fabs(cb[ci])));
+        mx = std::max(mx, std::fabs(cb[ci]));
     }
-    for (size_t ci = 0; ci < tp; ++ci) {
+    for (size_t ci = 0; ci < (size_t)d * tp; ++ci)
         if (std::fabs(ca[ci]) <= 1e-13 * mx) ca[ci] = 0.0;
+    for (size_t ci = 0; ci < tp; ++ci)
         if (std::fabs(cb[ci]) <= 1e-13 * mx) cb[ci] = 0.0;
-    }
     set_pattern(F, pattern_offsets(d, T, ca, cb));
     if (plan_factor(F, buf, store != LGP_F64) > buf_bytes) {
         factor_release(hF->F);
         delete hF;
         return LGP_E_NOMEM;
     }
-    if (hipMemcpyAsync(F.coefA, ca.data(), tp * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+    if (hipMemcpyAsync(F.coefA, ca.data(), (size_t)d * tp * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(F.coefB, cb.data(), tp * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
         hipStreamSynchronize(s);   // ca, cb must outlive their queued copies
         factor_release(hF->F);
@@ -349,6 +394,12 @@ lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* bu
     }
     *out = hF;
     return LGP_OK;
+}
+
+lgp_status lgp_factor_M(lgp_problem p, int Ta, int Tb, lgp_dtype store, void* buf, size_t buf_bytes, void* stream,
+                        lgp_factor* out) {
+    const int Tdir[3] = {Ta, Ta, Ta};
+    return lgp_factor_M_dir(p, Tdir, Tb, store, buf, buf_bytes, stream, out);
 }
 
 void lgp_destroy_factor(lgp_factor m) {

@@ -134,60 +134,56 @@ size_t const_factor_bytes(const Problem& P) {
     c.take<double>(n);
     c.take<double>(n);
     c.take<double>(n);
-    c.take<double>(2 * 256 + 2);
+    c.take<double>(4 * 256 + 4);
     return c.off + 256;
 }
 
-// per-block partial sums of W*b and W*a (the FDLT coefficient of index 0 is
-// the weighted mean: c_0 = 2^-d sum W f)
-__global__ void cc_partial_kernel(int64_t nq, const double* __restrict__ wab, double* __restrict__ part) {
-    __shared__ double sb[256], sa[256];
-    double vb = 0.0, va = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nq; i += (int64_t)gridDim.x * 256) {
-        vb += wab[i];
-        va += wab[nq + i];
-    }
-    sb[threadIdx.x] = vb;
-    sa[threadIdx.x] = va;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            sb[threadIdx.x] += sb[threadIdx.x + o];
-            sa[threadIdx.x] += sa[threadIdx.x + o];
+// per-block partial sums of the 1+d weighted fields W*b, W*a_{d-1}, .., W*a_0
+// (the FDLT coefficient of index 0 is the weighted mean: c_0 = 2^-d sum W f)
+__global__ void cc_partial_kernel(int64_t nq, int nf, const double* __restrict__ wab, double* __restrict__ part) {
+    __shared__ double sv[256];
+    for (int f = 0; f < nf; ++f) {
+        double v = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nq; i += (int64_t)gridDim.x * 256)
+            v += wab[(int64_t)f * nq + i];
+        sv[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) sv[threadIdx.x] += sv[threadIdx.x + o];
+            __syncthreads();
         }
+        if (threadIdx.x == 0) part[f * 256 + blockIdx.x] = sv[0];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = sb[0];
-        part[256 + blockIdx.x] = sa[0];
-    }
 }
 
+// part[1024 + f] = field f's mean: f = 0 is c_b, f = 1 + (d-1-j) is c_a of direction j
 __global__ void cc_final_kernel(int d, double* __restrict__ part) {
     if (threadIdx.x != 0) return;
-    double sb = 0.0, sa = 0.0;
-    for (int i = 0; i < 256; ++i) {
-        sb += part[i];
-        sa += part[256 + i];
+    const double scale = (d == 1) ? 0.5 : (d == 2) ? 0.25 : 0.125;   // 1 / |Omega|
+    for (int f = 0; f <= d; ++f) {
+        double v = 0.0;
+        for (int i = 0; i < 256; ++i) v += part[f * 256 + i];
+        part[1024 + f] = v * scale;
     }
-    const double scale = (d == 2) ? 0.25 : 0.125;
-    part[512] = sa * scale;   // c_a
-    part[513] = sb * scale;   // c_b
 }
 
-// 1 / (c_a sum_{pairs} lam lam' + c_b prod lam): for V[l][j][i] (3D) or V[j][i] (2D)
+// 1 / (sum_j c_j prod_{k != j} lam_k + c_b prod_k lam_k): in the eigenbasis the
+// stiffness of direction j becomes 1 and every mass factor its eigenvalue;
+// V[l][j][i] (3D) or V[j][i] (2D), i along x
 __global__ void cc_inverse_kernel(int d, int n1, int64_t n, const double* __restrict__ lam,
                                   const double* __restrict__ cc, double* __restrict__ inv) {
-    const double ca = cc[512], cb = cc[513];
+    const double cb = cc[1024];
+    const double cx = cc[1024 + d], cy = d >= 2 ? cc[1024 + d - 1] : 0.0, cz = d == 3 ? cc[1025] : 0.0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(e % n1);
         const int j = (int)((e / n1) % n1);
         double den;
         if (d == 2) {
-            den = ca * (lam[j] + lam[i]) + cb * lam[j] * lam[i];
+            den = cx * lam[j] + cy * lam[i] + cb * lam[j] * lam[i];
         } else {
             const int l = (int)(e / ((int64_t)n1 * n1));
-            den = ca * (lam[j] * lam[i] + lam[l] * lam[i] + lam[l] * lam[j]) + cb * lam[l] * lam[j] * lam[i];
+            den = cx * lam[l] * lam[j] + cy * lam[l] * lam[i] + cz * lam[j] * lam[i] + cb * lam[l] * lam[j] * lam[i];
         }
         inv[e] = 1.0 / den;
     }
@@ -209,11 +205,11 @@ lgp_status const_factor_build(Factor& F, Problem& P, void* buf, size_t bytes, hi
     F.ccInv = c.take<double>(P.n);
     F.ccT1 = c.take<double>(P.n);
     F.ccT2 = c.take<double>(P.n);
-    F.ccPart = c.take<double>(2 * 256 + 2);
+    F.ccPart = c.take<double>(4 * 256 + 4);
     F.bytes = c.off + 256;
     LGP_HIP(hipMemcpyAsync(F.ccE, cb.E.data(), cb.E.size() * 8, hipMemcpyHostToDevice, s));
     LGP_HIP(hipMemcpyAsync(F.ccLam, cb.lam.data(), cb.lam.size() * 8, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(cc_partial_kernel, dim3(256), dim3(256), 0, s, P.nq, (const double*)P.wab, F.ccPart);
+    hipLaunchKernelGGL(cc_partial_kernel, dim3(256), dim3(256), 0, s, P.nq, 1 + P.d, (const double*)P.wab, F.ccPart);
     hipLaunchKernelGGL(cc_final_kernel, dim3(1), dim3(64), 0, s, P.d, F.ccPart);
     hipLaunchKernelGGL(cc_inverse_kernel, dim3((unsigned)std::min<int64_t>(4096, (P.n + 255) / 256)), dim3(256), 0,
                        s, P.d, n1, P.n, (const double*)F.ccLam, (const double*)F.ccPart, F.ccInv);

@@ -103,7 +103,7 @@ size_t plan_factor(Factor& F, void* buf, bool with32) {
     F.prog = c.take<unsigned>((size_t)2 * F.nlines);
     F.ticket = c.take<unsigned>(4);
     F.flag = c.take<int>(4);
-    F.coefA = c.take<double>(tp);
+    F.coefA = c.take<double>((size_t)d * tp);
     F.coefB = c.take<double>(tp);
     F.band = c.take<double>((size_t)2 * (T + 1) * n1 * (2 * h + 1));
     F.pair_ptr = c.take<int>(nlo + 2);
@@ -200,7 +200,10 @@ struct RowGeo {
 //   Fa[t] = sum_{r,s} a_{r s t} M^(r)(iz, iz+dz) M^(s)(iy, iy+dy)
 //   Fb[t] = sum_{r,s} a_{r s t} [M^(r)_z S^(s)_y + S^(r)_z M^(s)_y] + b_{r s t} M^(r)_z M^(s)_y
 // so that M(i, i+delta) = sum_t S^(t)(ix, ix+dx) Fa[t] + M^(t)(ix, ix+dx) Fb[t]
-// (Kronecker form of Sec. 4.2; in 2D the z factors are 1 and r = 0).
+// (Kronecker form of Sec. 4.2; in 2D the z factors are 1 and r = 0). The
+// term with S in direction j carries a_j's series (coefA + j (T+1)^d), so
+// the same fold serves the isotropic form (three equal series) and the
+// anisotropic one of Example 4.
 // Layout: fold[line][(dz+h)*(2h+1) + (dy+h)][2][T+1].
 __global__ void fold_kernel(int d, int n1, int T, int h, const double* __restrict__ band,
                             const double* __restrict__ coefA, const double* __restrict__ coefB,
@@ -211,6 +214,7 @@ __global__ void fold_kernel(int d, int n1, int T, int h, const double* __restric
     const double* Sb = band;                         // S^(t)(i, i+delta)
     const double* Mb = band + (int64_t)T1 * bandT;   // M^(t)(i, i+delta)
     const int nz = (d == 3) ? W : 1;
+    const int64_t tp = (d == 3) ? (int64_t)T1 * T1 * T1 : (int64_t)T1 * T1;
     for (int line = blockIdx.x; line < nlines; line += gridDim.x) {
         const int iy = line % n1, iz = line / n1;
         const int combos = nz * W * T1;
@@ -235,9 +239,10 @@ __global__ void fold_kernel(int d, int n1, int T, int h, const double* __restric
                         const double my = Mb[s * bandT + (int64_t)iy * W + (dy + h)];
                         const double sy = Sb[s * bandT + (int64_t)iy * W + (dy + h)];
                         const int64_t ci = ((int64_t)r * T1 + s) * T1 + t;   // x fastest
-                        const double a = coefA[ci], b = coefB[ci];
-                        fa += a * mz * my;
-                        fb += a * (mz * sy + sz * my) + b * mz * my;
+                        const double ax = coefA[ci], ay = coefA[tp + ci];
+                        const double az = (d == 3) ? coefA[2 * tp + ci] : 0.0, b = coefB[ci];
+                        fa += ax * mz * my;
+                        fb += ay * mz * sy + az * sz * my + b * mz * my;
                     }
                 }
             }

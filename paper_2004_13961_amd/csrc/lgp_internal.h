@@ -70,8 +70,10 @@ struct Problem {
     double* PhiD;   // [2q][n1]  : [Phi ; D]
     double* DP;     // [2q][n1]  : [D ; Phi]
     double* Wnodes; // [nq] tensor weights
-    double* wab;    // [2][nq]   : W*b then W*a
-    double* a_nodes;// [nq]  copy of a
+    double* wab;    // [1+d][nq] : W*b, then W*a_j for j = d-1 .. 0 (z, y, x: the
+                    //             field of the derivative the stage takes)
+    double* a_nodes;// [d][nq] copy of a_j (x first); isotropic: a in slot 0 only
+    bool aniso;     // one diffusion field per direction (Example 4)
     double* b_nodes;// [nq]  copy of b
     // FP32 copies for the low-precision matvec
     float* PDT32; float* PhiD32; float* DP32; float* wab32;
@@ -92,6 +94,7 @@ lgp_status load_vector(Problem& P, const double* f, double* F, hipStream_t s);
 struct Factor {
     Problem* P;
     int d, n1, Ta, Tb, T, h;   // h = reach of the pattern per direction
+    int Tdir[3];               // truncation of a_j per direction (all Ta if isotropic)
     int64_t n;
     int noff, nlo;             // pattern size, number of strictly lower offsets
     int ldl;                   // row stride of L / Ut (>= nlo + 1, multiple of 32 doubles)
@@ -110,7 +113,7 @@ struct Factor {
     unsigned* prog;   // [2][nlines] progress counters (fwd, bwd)
     unsigned* ticket; // [4]
     int* flag;        // [4] device flags
-    double* coefA;    // [(T+1)^d] truncated coefficients of a (x fastest)
+    double* coefA;    // [d][(T+1)^d] truncated coefficients of a_j (x fastest), j = 0 (x) first
     double* coefB;    // [(T+1)^d]
     double* band;     // [2][T+1][n1][2h+1]  S^(t)(i, i+delta), M^(t)(i, i+delta)
     int* pair_ptr;    // [nlo+1]  CSR over k: rows j > k with offset(k)-offset(j) lower
@@ -136,7 +139,7 @@ struct Factor {
     double* ccInv = nullptr;   // [n1^d] 1 / eigenvalues of the transformed operator
     double* ccT1 = nullptr;    // [n1^d] scratch
     double* ccT2 = nullptr;    // [n1^d] scratch
-    double* ccPart = nullptr;  // [2*256 + 2] partial sums, then (c_a, c_b)
+    double* ccPart = nullptr;  // [4*256 + 4] partial sums per field, then the means (c_b, c_a of z, y, x)
     double* y_tmp;    // [n] intermediate of precond_apply
     bool has32;
     size_t bytes;
@@ -160,6 +163,8 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
                           size_t ws_bytes, hipStream_t s, lgp_solve_info* info);
 lgp_status build_tables(Problem& P, hipStream_t s);
 lgp_status setup_nodes(Problem& P, const double* a, const double* b, hipStream_t s, bool* coef_ok);
+// offset of the weighted field of direction j (0 = x) in wab / wab32
+inline int64_t wa_offset(const Problem& P, int j) { return (int64_t)(1 + (P.d - 1 - j)) * P.nq; }
 
 // host helpers
 void gauss_legendre_host(int N, std::vector<double>& x, std::vector<double>& w);

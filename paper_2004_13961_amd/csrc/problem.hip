@@ -68,13 +68,13 @@ size_t plan_problem(Problem& P, void* buf) {
     P.PhiD = c.take<double>(tab);
     P.DP = c.take<double>(tab);
     P.Wnodes = c.take<double>(P.nq);
-    P.wab = c.take<double>(2 * P.nq);
-    P.a_nodes = c.take<double>(P.nq);
+    P.wab = c.take<double>((size_t)(1 + P.d) * P.nq);
+    P.a_nodes = c.take<double>((size_t)P.d * P.nq);
     P.b_nodes = c.take<double>(P.nq);
     P.PDT32 = c.take<float>(tab);
     P.PhiD32 = c.take<float>(tab);
     P.DP32 = c.take<float>(tab);
-    P.wab32 = c.take<float>(2 * P.nq);
+    P.wab32 = c.take<float>((size_t)(1 + P.d) * P.nq);
     if (P.d == 1) {
         P.s0n = (size_t)2 * q;
         P.s1n = (size_t)2 * q;
@@ -115,7 +115,9 @@ size_t plan_problem(Problem& P, void* buf) {
 }
 
 // ------------------------------------------------------------ kernels ----
-__global__ void node_setup_kernel(int d, int q, int64_t nq, const double* __restrict__ w1,
+// nadir = 1: one diffusion field a for every direction; nadir = d: field j
+// (x first) at a + j*nq. wab gets W*b, then W*a_j for j = d-1 down to 0.
+__global__ void node_setup_kernel(int d, int q, int64_t nq, int nadir, const double* __restrict__ w1,
                                   const double* __restrict__ a, const double* __restrict__ b,
                                   double* __restrict__ W, double* __restrict__ wab,
                                   float* __restrict__ wab32, int* flag) {
@@ -127,15 +129,21 @@ __global__ void node_setup_kernel(int d, int q, int64_t nq, const double* __rest
             wt *= w1[r % q];
             r /= q;
         }
-        const double av = a[idx], bv = b[idx];
+        const double bv = b[idx];
         W[idx] = wt;
         wab[idx] = wt * bv;
-        wab[nq + idx] = wt * av;
         wab32[idx] = (float)(wt * bv);
-        wab32[nq + idx] = (float)(wt * av);
-        // a > 0 and both finite at every node (the bound on b is checked
+        bool bad = !isfinite(bv);
+        for (int j = 0; j < d; ++j) {
+            const double av = a[(nadir == 1 ? 0 : (int64_t)j * nq) + idx];
+            const int64_t o = (int64_t)(1 + (d - 1 - j)) * nq + idx;
+            wab[o] = wt * av;
+            wab32[o] = (float)(wt * av);
+            bad = bad || !(av > 0.0) || !isfinite(av);
+        }
+        // a_j > 0 and all finite at every node (the bound on b is checked
         // globally, see coef_min_kernel)
-        if (!(av > 0.0) || !isfinite(av) || !isfinite(bv)) atomicOr(flag, 1);
+        if (bad) atomicOr(flag, 1);
     }
 }
 
@@ -145,14 +153,14 @@ __global__ void node_setup_kernel(int d, int q, int64_t nq, const double* __rest
 // Poincare constant of (-1,1)^d, |grad u|^2 >= d pi^2 / 4 |u|^2, the form is
 // positive definite when min b > -(d pi^2 / 4) min a. Per-block minima, then
 // one block compares.
-__global__ void coef_min_kernel(int64_t nq, const double* __restrict__ a, const double* __restrict__ b,
+__global__ void coef_min_kernel(int64_t nq, int64_t na, const double* __restrict__ a, const double* __restrict__ b,
                                 double* __restrict__ part) {
     __shared__ double sa[256], sb[256];
     double ma = INFINITY, mb = INFINITY;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nq; i += (int64_t)gridDim.x * 256) {
-        ma = fmin(ma, a[i]);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < na; i += (int64_t)gridDim.x * 256)
+        ma = fmin(ma, a[i]);   // over every diffusion field
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nq; i += (int64_t)gridDim.x * 256)
         mb = fmin(mb, b[i]);
-    }
     sa[threadIdx.x] = ma;
     sb[threadIdx.x] = mb;
     __syncthreads();
@@ -281,15 +289,16 @@ lgp_status build_tables(Problem& P, hipStream_t s) {
 }
 
 lgp_status setup_nodes(Problem& P, const double* a, const double* b, hipStream_t s, bool* coef_ok) {
-    LGP_HIP(hipMemcpyAsync(P.a_nodes, a, P.nq * 8, hipMemcpyDeviceToDevice, s));
+    const int nadir = P.aniso ? P.d : 1;
+    LGP_HIP(hipMemcpyAsync(P.a_nodes, a, (size_t)nadir * P.nq * 8, hipMemcpyDeviceToDevice, s));
     LGP_HIP(hipMemcpyAsync(P.b_nodes, b, P.nq * 8, hipMemcpyDeviceToDevice, s));
     LGP_HIP(hipMemsetAsync(P.flag, 0, 4 * sizeof(int), s));
     // the 1D weights ride in the first q doubles of scratch s2
     LGP_HIP(hipMemcpyAsync(P.s2, P.w.data(), P.q * 8, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(node_setup_kernel, dim3(grid_for(P.nq)), dim3(256), 0, s, P.d, P.q, P.nq,
+    hipLaunchKernelGGL(node_setup_kernel, dim3(grid_for(P.nq)), dim3(256), 0, s, P.d, P.q, P.nq, nadir,
                        (const double*)P.s2, P.a_nodes, P.b_nodes, P.Wnodes, P.wab, P.wab32, P.flag);
     const int nb = (int)std::min<int64_t>(256, (P.nq + 255) / 256);
-    hipLaunchKernelGGL(coef_min_kernel, dim3(nb), dim3(256), 0, s, P.nq, (const double*)P.a_nodes,
+    hipLaunchKernelGGL(coef_min_kernel, dim3(nb), dim3(256), 0, s, P.nq, (int64_t)nadir * P.nq, (const double*)P.a_nodes,
                        (const double*)P.b_nodes, P.cmin);
     hipLaunchKernelGGL(coef_bound_kernel, dim3(1), dim3(64), 0, s, P.d, nb, P.cmin, P.flag);
     LGP_CHECK_LAUNCH();
@@ -332,7 +341,7 @@ static lgp_status matvec_impl(Problem& P, const T* u, T* y, GemmMode mode, const
         // stage 2a: [g0; gy] = ([Phi; D] T1) .* [Wb; Wa]  (2q x q)
         GEMM({PhiD, 0, n1, 1, s0, 0, 2 * q, 1, s1, 0, q, 1, wab, 0, q, 1, 2 * q, q, n1, 1, 0});
         // stage 2b: gx = (Phi T2) .* Wa                    (q x q)
-        GEMM({PhiD, 0, n1, 1, s0 + q, 0, 2 * q, 1, s2, 0, q, 1, wab + nq, 0, q, 1, q, q, n1, 1, 0});
+        GEMM({PhiD, 0, n1, 1, s0 + q, 0, 2 * q, 1, s2, 0, q, 1, wab + wa_offset(P, 0), 0, q, 1, q, q, n1, 1, 0});
         // stage 3a: Ax = Phi^T gx                          (n1 x q) -> s3[:, :q]
         GEMM({PDT, 0, 2 * q, 1, s2, 0, q, 1, s3, 0, 2 * q, 1, nullptr, 0, 0, 0, n1, q, q, 1, 0});
         // stage 3b: A0y = Phi^T g0 + D^T gy                (n1 x q) -> s3[:, q:]
@@ -353,9 +362,9 @@ static lgp_status matvec_impl(Problem& P, const T* u, T* y, GemmMode mode, const
     // Z1a: [g0; gz] = ([Phi; D] over z applied to Tphiphi) .* [Wb; Wa]
     GEMM({PhiD, 0, n1, 1, s1, 0, 2 * qq, 1, s2, 0, qq, 1, wab, 0, qq, 1, 2 * q, (int)qq, n1, 1, 0});
     // Z1b: gy = (Phi_z Tdphi) .* Wa
-    GEMM({PhiD, 0, n1, 1, s1 + qq, 0, 2 * qq, 1, s2 + 2 * q3, 0, qq, 1, wab + nq, 0, qq, 1, q, (int)qq, n1, 1, 0});
+    GEMM({PhiD, 0, n1, 1, s1 + qq, 0, 2 * qq, 1, s2 + 2 * q3, 0, qq, 1, wab + wa_offset(P, 1), 0, qq, 1, q, (int)qq, n1, 1, 0});
     // Z1c: gx = (Phi_z R2) .* Wa
-    GEMM({PhiD, 0, n1, 1, R2, 0, qq, 1, s2 + 3 * q3, 0, qq, 1, wab + nq, 0, qq, 1, q, (int)qq, n1, 1, 0});
+    GEMM({PhiD, 0, n1, 1, R2, 0, qq, 1, s2 + 3 * q3, 0, qq, 1, wab + wa_offset(P, 0), 0, qq, 1, q, (int)qq, n1, 1, 0});
     // Z2a: Zb[iz][0] = Phi_z^T g0 + D_z^T gz
     GEMM({PDT, 0, 2 * q, 1, s2, 0, qq, 1, s3, 0, 3 * qq, 1, nullptr, 0, 0, 0, n1, (int)qq, 2 * q, 1, 0});
     // Z2b: Zb[iz][1] = Phi_z^T gy

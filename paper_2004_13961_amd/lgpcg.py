@@ -25,8 +25,9 @@ STATUS = {
 
 EXPORTS = [
     "lgp_version", "lgp_status_str", "lgp_last_hip_error", "lgp_gauss_legendre",
-    "lgp_problem_bytes", "lgp_build_problem", "lgp_destroy_problem", "lgp_load_vector",
-    "lgp_matvec", "lgp_factor_bytes", "lgp_factor_M", "lgp_destroy_factor",
+    "lgp_problem_bytes", "lgp_build_problem", "lgp_build_problem_diag", "lgp_destroy_problem", "lgp_load_vector",
+    "lgp_matvec", "lgp_factor_bytes", "lgp_factor_M", "lgp_factor_bytes_dir", "lgp_factor_M_dir",
+    "lgp_destroy_factor",
     "lgp_precond_apply", "lgp_ilu_forward", "lgp_ilu_backward", "lgp_factor_describe",
     "lgp_solve_workspace_bytes", "lgp_pcg_solve", "lgp_factor_const_bytes", "lgp_factor_const",
 ]
@@ -77,11 +78,14 @@ def lib():
         "lgp_gauss_legendre": (i32, [i32, dp, dp]),
         "lgp_problem_bytes": (sz, [i32, i32]),
         "lgp_build_problem": (i32, [i32, i32, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]),
+        "lgp_build_problem_diag": (i32, [i32, i32, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]),
         "lgp_destroy_problem": (None, [vp]),
         "lgp_load_vector": (i32, [vp, vp, vp, vp]),
         "lgp_matvec": (i32, [vp, vp, vp, i32, vp]),
         "lgp_factor_bytes": (sz, [vp, i32, i32, i32]),
         "lgp_factor_M": (i32, [vp, i32, i32, i32, vp, sz, vp, ctypes.POINTER(vp)]),
+        "lgp_factor_bytes_dir": (sz, [vp, ctypes.POINTER(i32), i32, i32]),
+        "lgp_factor_M_dir": (i32, [vp, ctypes.POINTER(i32), i32, i32, vp, sz, vp, ctypes.POINTER(vp)]),
         "lgp_destroy_factor": (None, [vp]),
         "lgp_factor_const_bytes": (sz, [vp]),
         "lgp_factor_const": (i32, [vp, vp, sz, vp, ctypes.POINTER(vp)]),

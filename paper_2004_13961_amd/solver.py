@@ -29,7 +29,9 @@ def _need(t: torch.Tensor, dtype, numel: int, name: str):
 
 class Problem:
     """The operator K = A + B for nodal coefficients a, b on the (N+1)^d
-    Legendre-Gauss grid (x fastest)."""
+    Legendre-Gauss grid (x fastest). a_nodes holds one field ((N+1)^d values)
+    or, for the anisotropic form of Example 4, d fields one after the other
+    (a_1 for x first)."""
 
     def __init__(self, d: int, N: int, a_nodes: torch.Tensor, b_nodes: torch.Tensor):
         L = lib()
@@ -37,15 +39,17 @@ class Problem:
         self.n1, self.q = N - 1, N + 1
         self.n = self.n1 ** d
         self.nq = self.q ** d
-        _need(a_nodes, torch.float64, self.nq, "a_nodes")
+        self.aniso = a_nodes.numel() == d * self.nq and d > 1
+        _need(a_nodes, torch.float64, d * self.nq if self.aniso else self.nq, "a_nodes")
         _need(b_nodes, torch.float64, self.nq, "b_nodes")
         nbytes = L.lgp_problem_bytes(d, N)
         if nbytes == 0:
             raise lgpcg.LgpError(1, "lgp_problem_bytes")
         self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         h = ctypes.c_void_p()
-        check(L.lgp_build_problem(d, N, _ptr(a_nodes), _ptr(b_nodes), _ptr(self.buf), nbytes, _stream(),
-                                  ctypes.byref(h)), "lgp_build_problem")
+        build = L.lgp_build_problem_diag if self.aniso else L.lgp_build_problem
+        check(build(d, N, _ptr(a_nodes), _ptr(b_nodes), _ptr(self.buf), nbytes, _stream(), ctypes.byref(h)),
+              "lgp_build_problem")
         self.handle = h
 
     def __del__(self):
@@ -72,20 +76,27 @@ class Problem:
 
 
 class Factor:
-    """ILU(0) factors of the preconditioner M (truncations Ta for a, Tb for b)."""
+    """ILU(0) factors of the preconditioner M (truncations Ta for a, Tb for b;
+    Ta may be a sequence of d per-direction truncations t_1j, Example 4)."""
 
-    def __init__(self, problem: Problem, Ta: int, Tb: int = None, store: str = "f64"):
+    def __init__(self, problem: Problem, Ta, Tb: int = None, store: str = "f64"):
         L = lib()
-        Tb = Ta if Tb is None else Tb
+        if isinstance(Ta, (list, tuple)):
+            if Tb is None:
+                raise ValueError("Tb is required with per-direction Ta")
+            Tdir = (ctypes.c_int * 3)(*(list(Ta) + [0] * (3 - len(Ta))))
+        else:
+            Tb = Ta if Tb is None else Tb
+            Tdir = (ctypes.c_int * 3)(Ta, Ta, Ta)
         self.problem = problem
         self.Ta, self.Tb = Ta, Tb
-        nbytes = L.lgp_factor_bytes(problem.handle, Ta, Tb, DTYPES[store])
+        nbytes = L.lgp_factor_bytes_dir(problem.handle, Tdir, Tb, DTYPES[store])
         if nbytes == 0:
-            raise lgpcg.LgpError(1, "lgp_factor_bytes")
+            raise lgpcg.LgpError(1, "lgp_factor_bytes_dir")
         self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         h = ctypes.c_void_p()
-        check(L.lgp_factor_M(problem.handle, Ta, Tb, DTYPES[store], _ptr(self.buf), nbytes, _stream(),
-                             ctypes.byref(h)), "lgp_factor_M")
+        check(L.lgp_factor_M_dir(problem.handle, Tdir, Tb, DTYPES[store], _ptr(self.buf), nbytes, _stream(),
+                                 ctypes.byref(h)), "lgp_factor_M_dir")
         self.handle = h
 
     @classmethod

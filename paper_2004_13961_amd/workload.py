@@ -81,3 +81,15 @@ def paper_example_nodal(case: str, d: int, N: int):
     else:
         raise ValueError(case)
     return np.ascontiguousarray(a), np.ascontiguousarray(b), np.ones((N + 1,) * d)
+
+
+def paper_example4_nodal(d: int, N: int):
+    """(a_dir, b, f) at the library nodes for the anisotropic Example 4
+    (Sec. 5.2): a_1 = exp(2x), a_2 = cos(y), a_3 = cos(z) (d = 3), b = 0,
+    f = 1 (not stated in the paper). a_dir holds the d fields one after the
+    other, each on the full grid, x fastest."""
+    xs, _ = gauss_legendre(N)
+    X = _axis_coords(xs, d)
+    fields = [np.exp(2.0 * X[0])] + [np.cos(X[j]) for j in range(1, d)]
+    a_dir = np.concatenate([np.ascontiguousarray(f).reshape(-1) for f in fields])
+    return a_dir, np.zeros((N + 1,) * d), np.ones((N + 1,) * d)
