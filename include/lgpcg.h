@@ -181,7 +181,7 @@ lgp_status lgp_ilu_backward(lgp_factor m, const double* y, double* z, void* stre
  * k < n_lower, zero where the column leaves the grid, L[i*ld + n_lower]
  * = 1/U(i,i), and zero after that. D (device, n) holds the pivots U(i,i). */
 typedef struct {
-    int d, N, n1, Ta, Tb;
+    int d, N, n1, Ta, Tb;    /* Ta: the largest per-direction truncation, clamped to N */
     int64_t n;
     int noff, n_lower;
     const int* offsets;
@@ -192,7 +192,8 @@ typedef struct {
     double factor_kernel_ms; /* duration of the ILU(0) kernel of this factorisation,
                                 from HIP events on the caller's stream (-1 if unknown) */
     int factor_kernel;   /* which ILU(0) kernel built it: 2 = dataflow kernel (one row per
-                            wavefront, pair tables in LDS), 1 = generic level-ordered kernel.
+                            wavefront, pair tables in LDS), 1 = generic level-ordered kernel
+                            (for d = 1: the single-wavefront band factorisation).
                             The environment variable LGP_FACTOR_KERNEL=1|2 restricts the
                             choice to that kernel where it applies (else the generic one
                             runs); unset or 0 takes 2 where it applies. */

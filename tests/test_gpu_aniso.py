@@ -184,3 +184,25 @@ def test_example4_paper_tables(golden_dir):
             if not 4 * g[Ta] <= g[None]:
                 bad.append(("PCG-II not 4x below PCG-I", ex, N, Ta))
     assert not bad, bad
+
+
+def test_aniso_error_paths():
+    """Every field is checked: a_2 <= 0 at one node, or b below the
+    coercivity bound of the smallest field, is LGP_E_COEF; a truncation
+    outside 0..24 in any direction is LGP_E_ARG."""
+    from paper_2004_13961_amd.lgpcg import LgpError
+    from paper_2004_13961_amd.solver import Factor
+    d, N = 2, 12
+    a_dir, b = _fields(d, N, 3)
+    bad = [a_dir[0], a_dir[1].copy()]
+    bad[1].reshape(-1)[17] = -0.1
+    with pytest.raises(LgpError):
+        _problem(d, N, bad, b)
+    # min a over both fields is a_1's (0.5 .. 1.5); b = -(d pi^2/4) * 2 violates it
+    with pytest.raises(LgpError):
+        _problem(d, N, a_dir, np.full_like(b, -2.0 * 2.4674011002723395 * 2))
+    P = _problem(d, N, a_dir, b)
+    with pytest.raises(LgpError):
+        Factor(P, [4, 25], 2)
+    with pytest.raises(LgpError):
+        Factor(P, [-1, 3], 2)
