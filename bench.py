@@ -14,7 +14,7 @@ rate (factors built), the FP64 matvec rate against the matrix-core peak, the
 forward-sweep bandwidth, mixed-precision (FP32 and BF16 inner) solves, and the
 oracle on the host CPU (bounded sample).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2d_N1024_T8]
 """
 from __future__ import annotations
 
@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--workload", default="2d_N1024_T8", help="2d_N32_T4, 2d_N1024_T8, 3d_N128_T6 or 3d_N256_T6_mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=100000)
     ap.add_argument("--no-mixed", action="store_true")
@@ -147,7 +147,7 @@ def main():
     from paper_2004_13961_amd.solver import Factor, Problem, pcg_solve
     from paper_2004_13961_amd.workload import family_nodal
 
-    cfg = synth.CONFIGS[args.config]
+    cfg = synth.WORKLOADS[args.workload]
     d, N, T = cfg.d, cfg.N, cfg.T
     lgpcg.lib()
     a, b, f, _ = family_nodal(d, N, cfg.J, cfg.seed)

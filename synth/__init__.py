@@ -22,7 +22,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "Config", "CONFIGS", "coefficient_draws", "random_vector", "random_nodal",
+    "Config", "WORKLOADS", "coefficient_draws", "random_vector", "random_nodal",
     "serving_requests",
 ]
 
@@ -49,11 +49,11 @@ class Config:
         return (self.N - 1) ** self.d
 
 
-CONFIGS = {
-    0: Config("2d_N32_T4", d=2, N=32, T=4, J=6, seed=0, tol=1e-10),
-    1: Config("2d_N1024_T8", d=2, N=1024, T=8, J=12, seed=1, tol=1e-10),
-    2: Config("3d_N128_T6", d=3, N=128, T=6, J=6, seed=2, tol=1e-10),
-    3: Config("3d_N256_T6_mixed", d=3, N=256, T=6, J=6, seed=3, tol=1e-10,
+WORKLOADS = {
+    "2d_N32_T4": Config("2d_N32_T4", d=2, N=32, T=4, J=6, seed=0, tol=1e-10),
+    "2d_N1024_T8": Config("2d_N1024_T8", d=2, N=1024, T=8, J=12, seed=1, tol=1e-10),
+    "3d_N128_T6": Config("3d_N128_T6", d=3, N=128, T=6, J=6, seed=2, tol=1e-10),
+    "3d_N256_T6_mixed": Config("3d_N256_T6_mixed", d=3, N=256, T=6, J=6, seed=3, tol=1e-10,
               mixed=True, inner=("bf16", "f32")),
 }
 

@@ -47,8 +47,8 @@ class Case:
     def __init__(self, ci):
         from paper_2004_13961_amd.solver import Factor, Problem
         from paper_2004_13961_amd.workload import family_nodal
-        cfg = synth.CONFIGS[ci]
-        print("case config %d: d=%d N=%d T=%d" % (ci, cfg.d, cfg.N, cfg.T), flush=True)
+        cfg = synth.WORKLOADS[ci]
+        print("case %s: d=%d N=%d T=%d" % (ci, cfg.d, cfg.N, cfg.T), flush=True)
         self.cfg = cfg
         self.d, self.N, self.n1 = cfg.d, cfg.N, cfg.N - 1
         self.n = self.n1 ** cfg.d
@@ -155,7 +155,7 @@ def _golden_matvec(path):
     return meta, np.array(rows), np.array(vals)
 
 
-@pytest.mark.parametrize("ci", [1, 2])
+@pytest.mark.parametrize("ci", ["2d_N1024_T8", "3d_N128_T6"])
 def test_fullsize_load_vector_and_matvec(ci, golden_dir):
     """Load vector and K u over the whole grid against the FP64 oracle. In 2D
     at N = 1024 the FP64 sum factorisation itself drifts from the exact
@@ -169,18 +169,18 @@ def test_fullsize_load_vector_and_matvec(ci, golden_dir):
     y = _host(C.P.matvec(_dev(u)))
     ref = C.matvec_oracle(u)
     rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
-    if ci == 1:
+    if ci == "2d_N1024_T8":
         meta, rows, vals = _golden_matvec(os.path.join(golden_dir, "matvec_ext_2d_N1024.txt"))
         err = np.max(np.abs(y[rows] - vals)) / meta["norminf"]
-        print("config 1 matvec: sampled error vs extended precision %.2e, 2-norm vs FP64 oracle %.2e" % (err, rel))
+        print("2d_N1024_T8 matvec: sampled error vs extended precision %.2e, 2-norm vs FP64 oracle %.2e" % (err, rel))
         assert err <= 1e-12
         assert rel <= 1e-12 + meta["fp64_oracle_rel_err_norm2"]
     else:
-        print("config %d matvec: 2-norm vs FP64 oracle %.2e" % (ci, rel))
+        print("%s matvec: 2-norm vs FP64 oracle %.2e" % (ci, rel))
         assert rel <= 1e-12
 
 
-@pytest.mark.parametrize("ci,count", [(1, 48), (2, 6)])
+@pytest.mark.parametrize("ci,count", [("2d_N1024_T8", 48), ("3d_N128_T6", 6)])
 def test_fullsize_ilu0_equations(ci, count):
     """Sec. 4.3: (L D L^T)(i, i+d_k) = M(i, i+d_k) for every lower offset k
     and the diagonal, at sampled rows i."""
@@ -194,7 +194,7 @@ def test_fullsize_ilu0_equations(ci, count):
     # 1e-14 * max|coefficient|
     cerr = 1e-14 * max(np.max(np.abs(C.ah)), np.max(np.abs(C.bh)))
     worst = 0.0
-    for i in C.sample_rows(count, 1000 + ci):
+    for i in C.sample_rows(count, 1000 + C.cfg.seed):
         nb = [C.shifted(i, o) for o in lower]              # rows i + d_k
         need = [i] + [r for r in nb if r >= 0]
         Lr, Dr = _rows_of(C, need)
@@ -232,16 +232,16 @@ def test_fullsize_ilu0_equations(ci, count):
     print("ILU(0) equations: worst residual / allowance %.2e" % worst)
 
 
-@pytest.mark.parametrize("ci,count", [(1, 256), (2, 16)])
+@pytest.mark.parametrize("ci,count", [("2d_N1024_T8", 256), ("3d_N128_T6", 16)])
 def test_fullsize_sweeps(ci, count):
     """Alg. 3 and Alg. 4 at sampled rows: r_i = y_i + sum_k L(i,k) y(i+d_k) and
     y_i / D(i) = z_i + sum_k L(i-d_k, k) z(i-d_k)."""
     C = _case(ci)
-    r = synth.random_vector(C.n, 500 + ci)
+    r = synth.random_vector(C.n, 500 + C.cfg.seed)
     y = _host(C.M.forward(_dev(r)))
     z = _host(C.M.backward(_dev(y)))
     lower = C.offs[:C.nlo]
-    rows = C.sample_rows(count, 2000 + ci)
+    rows = C.sample_rows(count, 2000 + C.cfg.seed)
     Lr, Dr = _rows_of(C, rows)
     for t, i in enumerate(rows):
         nb = np.array([C.shifted(i, o) for o in lower])
@@ -258,14 +258,14 @@ def test_fullsize_sweeps(ci, count):
         assert abs(res_b) <= 1e-12 * (abs(y[i] / Dr[t]) + np.abs(terms_b).sum()), ("backward", i, res_b)
 
 
-@pytest.mark.parametrize("ci", [1, 2])
+@pytest.mark.parametrize("ci", ["2d_N1024_T8", "3d_N128_T6"])
 def test_fullsize_pcg_fp64(ci):
     from paper_2004_13961_amd.solver import pcg_solve
     C = _case(ci)
     x, info = pcg_solve(C.P, C.M, C.F, rtol=C.cfg.tol)
     xg = _host(x)
     res = np.linalg.norm(C.F_o - C.matvec_oracle(xg)) / np.linalg.norm(C.F_o)
-    print("config %d FP64: iters %d, solver residual %.2e, oracle residual %.2e" % (
+    print("%s FP64: iters %d, solver residual %.2e, oracle residual %.2e" % (
         ci, info["iters"], info["relres_true"], res))
     assert info["relres_true"] <= C.cfg.tol
     assert res <= 1.5 * C.cfg.tol
@@ -274,12 +274,12 @@ def test_fullsize_pcg_fp64(ci):
 @pytest.mark.parametrize("inner", ["f32", "bf16"])
 def test_fullsize_pcg_mixed_2d(inner):
     from paper_2004_13961_amd.solver import Factor, pcg_solve
-    C = _case(1)
+    C = _case("2d_N1024_T8")
     M32 = Factor(C.P, C.cfg.T, store="f32")
     x, info = pcg_solve(C.P, M32, C.F, rtol=C.cfg.tol, inner=inner)
     xg = _host(x)
     res = np.linalg.norm(C.F_o - C.matvec_oracle(xg)) / np.linalg.norm(C.F_o)
-    print("config 1 mixed %s: outer %d, inner iters %d, oracle residual %.2e" % (
+    print("2d_N1024_T8 mixed %s: outer %d, inner iters %d, oracle residual %.2e" % (
         inner, info["outer"], info["iters"], res))
     assert info["relres_true"] <= C.cfg.tol
     assert res <= 1.5 * C.cfg.tol

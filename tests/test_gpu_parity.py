@@ -145,11 +145,11 @@ def _config_oracle(cfg, N=None):
     return B, a, b, F
 
 
-def test_pcg_config0_vs_oracle():
+def test_pcg_2d_N32_T4_vs_oracle():
     """2D, N = 32, T = 4, tol 1e-10 (the small benchmark configuration)."""
     from paper_2004_13961_amd.solver import Problem, Factor, pcg_solve
     from paper_2004_13961_amd.workload import family_nodal
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS["2d_N32_T4"]
     B, a_o, b_o, F_o = _config_oracle(cfg)
     st, _ = _oracle_factor(2, cfg.N, a_o, b_o, cfg.T, cfg.T)
     mv = lambda v: gk.matvec_sumfact(2, cfg.N, a_o, b_o, v, B)
@@ -169,10 +169,10 @@ def test_pcg_config0_vs_oracle():
 
 
 @pytest.mark.parametrize("inner", ["f32", "bf16"])
-def test_pcg_mixed_config0(inner):
+def test_pcg_mixed_2d_N32_T4(inner):
     from paper_2004_13961_amd.solver import Problem, Factor, pcg_solve
     from paper_2004_13961_amd.workload import family_nodal
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS["2d_N32_T4"]
     B, a_o, b_o, F_o = _config_oracle(cfg)
     a_g, b_g, f_g, _ = family_nodal(2, cfg.N, cfg.J, cfg.seed)
     P = Problem(2, cfg.N, _dev(a_g).reshape(-1), _dev(b_g).reshape(-1))

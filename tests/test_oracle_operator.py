@@ -167,8 +167,8 @@ def test_mutations_are_caught():
     assert np.linalg.norm(bad - y0) > 1e-4 * np.linalg.norm(y0)
 
 
-def test_pcg_matches_dense_solve_config0_family():
-    cfg = synth.CONFIGS[0]
+def test_pcg_matches_dense_solve_2d_N32_family():
+    cfg = synth.WORKLOADS["2d_N32_T4"]
     N = 16
     B = gk.Basis(N)
     c = synth.coefficient_draws(2, cfg.J, cfg.seed)

@@ -196,10 +196,10 @@ def test_1d_ilu0_is_banded_lu():
     assert np.linalg.norm(M @ z - r) < 1e-12 * np.linalg.norm(r)
 
 
-def test_pcg_ilu_config0_full():
-    """Config 0 (2D, N = 32, T = 4): PCG with the ILU(0) one-step
+def test_pcg_ilu_2d_N32_T4_full():
+    """2D, N = 32, T = 4: PCG with the ILU(0) one-step
     preconditioner reaches 1e-10 and agrees with the dense solve."""
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS["2d_N32_T4"]
     B, a, b, ah, bh = _config_problem(2, cfg.N, cfg.T, J=cfg.J, seed=cfg.seed)
     c = synth.coefficient_draws(2, cfg.J, cfg.seed)
     F = gk.load_vector(2, cfg.N, wl.rhs_f(c, B.x), B)
