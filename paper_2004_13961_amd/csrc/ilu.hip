@@ -1428,9 +1428,11 @@ __global__ __launch_bounds__(64) void band1d_factor_kernel(int n1, int nlo, int 
 template <typename T, bool REV>
 __global__ __launch_bounds__(64) void band1d_sweep_kernel(int n1, int nlo, int ldl, const int4* __restrict__ offs,
                                                           const T* __restrict__ A, const T* __restrict__ invd,
-                                                          const T* __restrict__ in, T* __restrict__ out) {
+                                                          const T* __restrict__ in, T* __restrict__ out,
+                                                          const int* __restrict__ stop) {
     __shared__ T win[64];
     const int lane = threadIdx.x;
+    if (stop && *stop) return;   // the solver has converged: nothing to do
     const int dl = lane < nlo ? offs[lane].x : 0;
     win[lane] = T(0);
     __syncthreads();
@@ -1498,13 +1500,13 @@ static lgp_status band1d_build(Factor& F, std::vector<int>& off4, hipStream_t s)
 
 template <typename T>
 static lgp_status band1d_sweep(Factor& F, bool backward, const T* A, const T* invd, const T* in, T* out,
-                               hipStream_t s) {
+                               hipStream_t s, const int* stop) {
     if (backward)
         hipLaunchKernelGGL((band1d_sweep_kernel<T, true>), dim3(1), dim3(64), 0, s, F.n1, F.nlo, F.ldl,
-                           (const int4*)F.d_offs, A, invd, in, out);
+                           (const int4*)F.d_offs, A, invd, in, out, stop);
     else
         hipLaunchKernelGGL((band1d_sweep_kernel<T, false>), dim3(1), dim3(64), 0, s, F.n1, F.nlo, F.ldl,
-                           (const int4*)F.d_offs, A, invd, in, out);
+                           (const int4*)F.d_offs, A, invd, in, out, stop);
     LGP_CHECK_LAUNCH();
     return LGP_OK;
 }
@@ -1919,7 +1921,7 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
 }
 
 lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStream_t s, const int* stop) {
-    if (F.d == 1) return band1d_sweep<double>(F, backward, F.L, F.invD, in, out, s);
+    if (F.d == 1) return band1d_sweep<double>(F, backward, F.L, F.invD, in, out, s, stop);
     if (backward && F.ut_ready) LGP_HIP(hipStreamWaitEvent(s, F.ut_ready, 0));
     return backward ? sweep_t<double>(F, true, F.Ut, F.invD, in, out, s, stop)
                     : sweep_t<double>(F, false, F.L, nullptr, in, out, s, stop);
@@ -1927,7 +1929,7 @@ lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStr
 
 lgp_status sweep32(Factor& F, bool backward, const float* in, float* out, hipStream_t s, const int* stop) {
     if (!F.has32) return LGP_E_ARG;
-    if (F.d == 1) return band1d_sweep<float>(F, backward, F.L32, F.invD32, in, out, s);
+    if (F.d == 1) return band1d_sweep<float>(F, backward, F.L32, F.invD32, in, out, s, stop);
     if (backward && F.ut_ready) LGP_HIP(hipStreamWaitEvent(s, F.ut_ready, 0));
     return backward ? sweep_t<float>(F, true, F.Ut32, F.invD32, in, out, s, stop)
                     : sweep_t<float>(F, false, F.L32, nullptr, in, out, s, stop);
