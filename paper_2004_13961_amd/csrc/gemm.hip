@@ -35,6 +35,7 @@ __device__ inline flt4 mfma16x16x4(float a, float b, flt4 c) {
 
 template <typename T, typename V4>
 __global__ __launch_bounds__(NT) void gemm_k4_kernel(GemmArgs g) {
+    if (g.stop && *g.stop) return;
     constexpr int BK = 16;
     __shared__ T As[BK][BM + 1];
     __shared__ T Bs[BK][BN + 1];
@@ -131,6 +132,7 @@ __global__ __launch_bounds__(NT) void gemm_k4_kernel(GemmArgs g) {
 
 // BF16 operands, FP32 data and accumulation.
 __global__ __launch_bounds__(NT) void gemm_bf16_kernel(GemmArgs g) {
+    if (g.stop && *g.stop) return;
     constexpr int BK = 32, PAD = 8;
     __shared__ __attribute__((aligned(16))) __bf16 As[BM][BK + PAD];   // [i][k]
     __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][BK + PAD];   // [j][k]

@@ -330,7 +330,7 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
             int it = 0;
             st = pcg_loop<double>(
                 n, x, S.r, S.z, S.p, S.w, S, o.max_iter - total, check_every,
-                [&](const double* pp, double* ww) { return matvec_f64(P, pp, ww, s); },
+                [&](const double* pp, double* ww) { return matvec_f64(P, pp, ww, s, S.fl); },
                 [&](const double* rr_, double* zz) {
                     if (M.kind == 1) return const_apply(M, rr_, zz, s);
                     lgp_status a = sweep(M, false, rr_, M.y_tmp, s, S.fl);
@@ -375,7 +375,7 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
         double rr = 0.0;
         st = pcg_loop<float>(
             n, S.e32, S.r32, S.z32, S.p32, S.w32, S, o.max_iter - total, check_every,
-            [&](const float* pp, float* ww) { return matvec_lp(P, pp, ww, mode, s); },
+            [&](const float* pp, float* ww) { return matvec_lp(P, pp, ww, mode, s, S.fl); },
             [&](const float* rr_, float* zz) {
                 lgp_status a = sweep32(M, false, rr_, S.y32, s, S.fl);
                 if (a != LGP_OK) return a;

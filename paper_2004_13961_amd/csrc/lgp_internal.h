@@ -56,6 +56,7 @@ struct GemmArgs {
     const void* E; int64_t sEb, sEi, sEj;
     int M, N, K, batch;
     int accumulate;
+    const int* stop = nullptr;   // device flag: when set, the launch returns at once (PCG has converged)
 };
 
 lgp_status gemm(GemmMode mode, const GemmArgs& g, hipStream_t s);
@@ -86,8 +87,8 @@ struct Problem {
 };
 
 size_t plan_problem(Problem& P, void* buf);
-lgp_status matvec_f64(Problem& P, const double* u, double* y, hipStream_t s);
-lgp_status matvec_lp(Problem& P, const float* u, float* y, GemmMode mode, hipStream_t s);
+lgp_status matvec_f64(Problem& P, const double* u, double* y, hipStream_t s, const int* stop = nullptr);
+lgp_status matvec_lp(Problem& P, const float* u, float* y, GemmMode mode, hipStream_t s, const int* stop = nullptr);
 lgp_status load_vector(Problem& P, const double* f, double* F, hipStream_t s);
 
 // ------------------------------------------------------------ factor -----

@@ -313,7 +313,7 @@ lgp_status setup_nodes(Problem& P, const double* a, const double* b, hipStream_t
 // Element-generic driver: `es` = element size (8 for FP64, 4 otherwise).
 template <typename T>
 static lgp_status matvec_impl(Problem& P, const T* u, T* y, GemmMode mode, const T* PDT, const T* PhiD,
-                              const T* DP, const T* wab, hipStream_t s) {
+                              const T* DP, const T* wab, hipStream_t s, const int* stop) {
     const int n1 = P.n1, q = P.q;
     const int64_t nq = P.nq;
     T* s0 = (T*)P.s0;
@@ -324,6 +324,7 @@ static lgp_status matvec_impl(Problem& P, const T* u, T* y, GemmMode mode, const
 #define GEMM(...)                                   \
     do {                                            \
         GemmArgs g_ = __VA_ARGS__;                  \
+        g_.stop = stop;                             \
         if ((st = gemm(mode, g_, s)) != LGP_OK) return st; \
     } while (0)
     // GemmArgs field order:
@@ -381,12 +382,12 @@ static lgp_status matvec_impl(Problem& P, const T* u, T* y, GemmMode mode, const
     return LGP_OK;
 }
 
-lgp_status matvec_f64(Problem& P, const double* u, double* y, hipStream_t s) {
-    return matvec_impl<double>(P, u, y, GEMM_F64, P.PDT, P.PhiD, P.DP, P.wab, s);
+lgp_status matvec_f64(Problem& P, const double* u, double* y, hipStream_t s, const int* stop) {
+    return matvec_impl<double>(P, u, y, GEMM_F64, P.PDT, P.PhiD, P.DP, P.wab, s, stop);
 }
 
-lgp_status matvec_lp(Problem& P, const float* u, float* y, GemmMode mode, hipStream_t s) {
-    return matvec_impl<float>(P, u, y, mode, P.PDT32, P.PhiD32, P.DP32, P.wab32, s);
+lgp_status matvec_lp(Problem& P, const float* u, float* y, GemmMode mode, hipStream_t s, const int* stop) {
+    return matvec_impl<float>(P, u, y, mode, P.PDT32, P.PhiD32, P.DP32, P.wab32, s, stop);
 }
 
 lgp_status load_vector(Problem& P, const double* f, double* F, hipStream_t s) {
