@@ -241,11 +241,13 @@ def main():
     dominant = max(share, key=share.get)
     if dominant == "factor":
         ach = factor_bytes / (fac_ms * 1e-3) / 1e9
-        roof = dict(kernel="ilu_factor2_kernel (ILU(0), Alg. 2)", bound="hbm", achieved=round(ach, 2),
+        fk = "ilu_factor2_kernel" if desc.get("factor_kernel") == 2 else "ilu_factor_kernel"
+        roof = dict(kernel=fk + " (ILU(0), Alg. 2)", bound="hbm", achieved=round(ach, 2),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 6),
                     bytes_per_launch=factor_bytes, launch_ms=round(fac_ms, 3))
     elif dominant == "sweep":
-        roof = dict(kernel="sweep2d_pair_kernel (forward substitution, Alg. 3)", bound="hbm",
+        sk = "sweep2d_pair_kernel" if d == 2 else "sweep_kernel"
+        roof = dict(kernel=sk + " (forward substitution, Alg. 3)", bound="hbm",
                     achieved=round(sw_gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(sw_gbs / HBM_PEAK_GBS, 5), bytes_per_launch=sweep_bytes,
                     launch_ms=round(sw_ms, 4))
