@@ -206,3 +206,28 @@ def test_aniso_error_paths():
         Factor(P, [4, 25], 2)
     with pytest.raises(LgpError):
         Factor(P, [-1, 3], 2)
+
+
+@pytest.mark.parametrize("inner", ["f32", "bf16"])
+def test_aniso_mixed_precision_solve(inner):
+    """Mixed solves of the anisotropic form: FP64 true residual to the
+    tolerance, checked again with the oracle's product; the BF16 product
+    within 3e-2 (operand rounding times contraction depth, as for the
+    isotropic form)."""
+    from paper_2004_13961_amd.solver import Factor, pcg_solve
+    d, N = 2, 100
+    a_dir, b = _fields(d, N, 71)
+    P = _problem(d, N, a_dir, b)
+    B = gk.Basis(N)
+    u = synth.random_vector((N - 1) ** d, 72)
+    ref = gk.matvec_sumfact(d, N, a_dir, b, u, B)
+    y16 = _host(P.matvec(torch.from_numpy(u.astype(np.float32)).cuda(), prec="bf16")).astype(np.float64)
+    assert np.linalg.norm(y16 - ref) <= 3e-2 * np.linalg.norm(ref)
+    F = _dev(synth.random_vector((N - 1) ** d, 73))
+    M = Factor(P, [5, 3], 2, store="f32")
+    x, info = pcg_solve(P, M, F, rtol=1e-10, inner=inner)
+    Fh = _host(F)
+    res = np.linalg.norm(Fh - gk.matvec_sumfact(d, N, a_dir, b, _host(x), B)) / np.linalg.norm(Fh)
+    print("aniso mixed %s: outer %d, inner iters %d, oracle residual %.2e" % (inner, info["outer"], info["iters"], res))
+    assert info["relres_true"] <= 1e-10
+    assert res <= 1.5e-10
