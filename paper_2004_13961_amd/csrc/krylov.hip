@@ -21,7 +21,7 @@ enum {
     SC_RHO = 0, SC_RHO_OLD, SC_PW, SC_RR, SC_ALPHA, SC_BETA, SC_FF, SC_THRESH2,
     SC_K, SC_KMAX, SC_COUNT = 16
 };
-enum { FL_DONE = 0, FL_BREAK = 1, FL_FIRST = 2, FL_COUNT = 4 };
+enum { FL_DONE = 0, FL_BREAK = 1, FL_FIRST = 2, FL_XZERO = 3, FL_COUNT = 4 };
 
 struct SolveWS {
     double* r; double* z; double* p; double* w;            // FP64
@@ -166,10 +166,26 @@ __global__ __launch_bounds__(VBS) void update_xr_kernel(int64_t n, T* __restrict
 }
 
 // r = F - w
+// r = F - w, or r = F when x was all zeros (then the product was skipped and
+// w holds nothing)
 __global__ void residual_kernel(int64_t n, const double* __restrict__ F, const double* __restrict__ w,
-                                double* __restrict__ r) {
+                                double* __restrict__ r, const int* __restrict__ xzero) {
+    const bool zero = *xzero != 0;
     for (int64_t i = blockIdx.x * (int64_t)VBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBS)
-        r[i] = F[i] - w[i];
+        r[i] = zero ? F[i] : F[i] - w[i];
+}
+
+__global__ void set_flag_kernel(int* f, int v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *f = v;
+}
+
+// *f = 0 if any entry of x is nonzero (NaN counts as nonzero); every writer
+// stores the same value
+__global__ void clear_if_nonzero_kernel(int64_t n, const double* __restrict__ x, int* f) {
+    bool nz = false;
+    for (int64_t i = blockIdx.x * (int64_t)VBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBS)
+        nz = nz || !(x[i] == 0.0);
+    if (__any(nz) && (threadIdx.x & 63) == 0) atomicExch(f, 0);
 }
 
 // r32 = r * scale ; e32 = 0
@@ -299,8 +315,14 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
     }
     auto true_residual = [&](double* relres) -> lgp_status {
         lgp_status st2;
-        if ((st2 = matvec_f64(P, x, S.w, s)) != LGP_OK) return st2;
-        hipLaunchKernelGGL(residual_kernel, dim3(vgrid(n)), dim3(VBS), 0, s, n, F, (const double*)S.w, S.r);
+        // K x is skipped when x is all zeros (the usual x_0): a flag set on
+        // the device, read by the contractions and the residual kernel
+        int* xzero = S.fl + FL_XZERO;
+        hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(64), 0, s, xzero, 1);
+        hipLaunchKernelGGL(clear_if_nonzero_kernel, dim3(vgrid(n)), dim3(VBS), 0, s, n, (const double*)x, xzero);
+        if ((st2 = matvec_f64(P, x, S.w, s, xzero)) != LGP_OK) return st2;
+        hipLaunchKernelGGL(residual_kernel, dim3(vgrid(n)), dim3(VBS), 0, s, n, F, (const double*)S.w, S.r,
+                           (const int*)xzero);
         hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, s, S.sc, S.fl, 0.0, 0.0, 0.0);
         hipLaunchKernelGGL(dot_kernel<double>, dim3(NPART), dim3(VBS), 0, s, n, (const double*)S.r,
                            (const double*)S.r, S.part, (const int*)S.fl);
