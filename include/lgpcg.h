@@ -24,11 +24,14 @@
  *     library and released by the matching destroy call.
  *   - Every function returns an lgp_status; nothing throws across the ABI.
  *     After a non-OK build or factor the handle is not created.
- *   - A handle must not be used from two host threads at once. Calls on one
- *     handle must be ordered on a single stream.
- *   - Requests on several streams driven from several host threads at once
- *     are not supported: one such run with three streams stopped making
- *     progress, for a reason not yet found. Issue requests from one thread.
+ *   - Calls on one handle must be ordered on a single stream.
+ *   - One host thread at a time: an entry point that enqueues device work,
+ *     called from a second thread while another thread is inside the
+ *     library, returns LGP_E_UNSUPPORTED without enqueueing anything.
+ *     Requests that should overlap on the device go through the batched
+ *     entry points below, from one thread. (Several request streams driven
+ *     from several threads once stopped making progress; the library now
+ *     uses only the caller's stream, but the case is not served.)
  */
 #ifndef LGPCG_H
 #define LGPCG_H
@@ -42,12 +45,13 @@ extern "C" {
 
 typedef enum {
     LGP_OK = 0,
-    LGP_E_ARG = 1,        /* bad argument: d not in {2,3}, N < 2, null pointer, T < 0 */
+    LGP_E_ARG = 1,        /* bad argument: d not in {1,2,3}, N out of range, null pointer, T out of
+                             range, or a NaN / infinity in F or in the initial guess of a solve */
     LGP_E_NOMEM = 2,      /* caller buffer smaller than the size query returned */
     LGP_E_COEF = 3,       /* a <= 0 or a non-finite value at a node, or min b <= -(d pi^2/4) min a */
     LGP_E_ILU_PIVOT = 4,  /* ILU(0) pivot <= 0 or non-finite (Alg. 2 assumes existence) */
     LGP_E_NOCONV = 5,     /* max_iter reached before the stop rule of Alg. 1 */
-    LGP_E_BREAKDOWN = 6,  /* p'Kp <= 0 or r'z <= 0 in PCG */
+    LGP_E_BREAKDOWN = 6,  /* p'Kp <= 0 or r'z <= 0 in PCG, or a non-finite residual after iterating */
     LGP_E_HIP = 7,        /* a HIP runtime call failed; see lgp_last_hip_error */
     LGP_E_UNSUPPORTED = 8 /* valid request the library does not serve */
 } lgp_status;

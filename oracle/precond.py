@@ -268,6 +268,55 @@ def M_row_entries(d: int, n1: int, ahat, bhat, row_idx, offsets,
     return (out, mag, pmag) if return_abs else out
 
 
+def M_rows_entries(d: int, n1: int, ahat, bhat, rows, offsets, S=None, Mm=None):
+    """M_row_entries for many rows at once: the same term-by-term sums of
+    Kronecker products of the 1D factors (Sec. 4.2), each term evaluated for
+    all (row, offset) pairs as one array. Returns (entries, magnitudes,
+    factor magnitudes), each of shape (len(rows), len(offsets))."""
+    T = max(ahat.shape[0], bhat.shape[0]) - 1
+    if S is None:
+        S, Mm = band_factors(n1, T)
+    rows = np.asarray(rows, dtype=np.int64)
+    offs = np.asarray(offsets, dtype=np.int64).reshape(len(offsets), -1)[:, :d]
+    coords = np.stack([(rows // n1 ** k) % n1 for k in range(d)], axis=1)      # (R, d)
+    col = coords[:, None, :] + offs[None, :, :]                                   # (R, K, d)
+    inside = np.all((col >= 0) & (col < n1), axis=2)
+    colc = np.clip(col, 0, n1 - 1)
+    out = np.zeros(inside.shape)
+    mag = np.zeros(inside.shape)
+    pmag = np.zeros(inside.shape)
+
+    def factor(F, t, k):
+        return F[t, coords[:, k][:, None], colc[:, :, k]]
+
+    def add(c, mats):
+        prod = np.ones(inside.shape)
+        for m in mats:
+            prod = prod * m
+        out[...] += c * prod
+        mag[...] += np.abs(c * prod)
+        if c != 0.0:
+            pmag[...] += np.abs(prod)
+
+    for idx in np.ndindex(*ahat.shape):
+        c = ahat[idx]
+        if c == 0.0:
+            continue
+        deg = idx[::-1]
+        for s_dir in range(d):
+            add(c, [factor(S if k == s_dir else Mm, deg[k], k) for k in range(d)])
+    for idx in np.ndindex(*bhat.shape):
+        c = bhat[idx]
+        if c == 0.0:
+            continue
+        deg = idx[::-1]
+        add(c, [factor(Mm, deg[k], k) for k in range(d)])
+    out[~inside] = 0.0
+    mag[~inside] = 0.0
+    pmag[~inside] = 0.0
+    return out, mag, pmag
+
+
 def pattern_mask(d: int, n1: int, offsets) -> np.ndarray:
     """Dense boolean NZ pattern for tiny n from the offset set."""
     n = n1 ** d

@@ -3,11 +3,34 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <mutex>
 #include <new>
+#include <thread>
 
 #include "lgp_internal.h"
 
 using namespace lgp;
+
+namespace lgp {
+static std::mutex g_guard_mu;
+static std::thread::id g_guard_owner;
+static int g_guard_depth = 0;
+
+ThreadGuard::ThreadGuard() {
+    std::lock_guard<std::mutex> lk(g_guard_mu);
+    const std::thread::id me = std::this_thread::get_id();
+    ok = (g_guard_depth == 0 || g_guard_owner == me);
+    if (ok) {
+        g_guard_owner = me;
+        ++g_guard_depth;
+    }
+}
+ThreadGuard::~ThreadGuard() {
+    if (!ok) return;
+    std::lock_guard<std::mutex> lk(g_guard_mu);
+    --g_guard_depth;
+}
+}  // namespace lgp
 
 struct lgp_problem_s {
     Problem P;
@@ -75,6 +98,7 @@ static lgp_status build_problem(int d, int N, const double* a_nodes, const doubl
     if (!out) return LGP_E_ARG;
     *out = nullptr;
     if (!valid_dims(d, N) || !a_nodes || !b_nodes || !buf) return LGP_E_ARG;
+    LGP_ONE_THREAD();
     lgp_problem_s* h = new (std::nothrow) lgp_problem_s();
     if (!h) return LGP_E_NOMEM;
     Problem& P = h->P;
@@ -111,11 +135,13 @@ void lgp_destroy_problem(lgp_problem p) { delete p; }
 
 lgp_status lgp_load_vector(lgp_problem p, const double* f_nodes, double* F, void* stream) {
     if (!p || !f_nodes || !F) return LGP_E_ARG;
+    LGP_ONE_THREAD();
     return load_vector(p->P, f_nodes, F, (hipStream_t)stream);
 }
 
 lgp_status lgp_matvec(lgp_problem p, const void* u, void* y, lgp_dtype prec, void* stream) {
     if (!p || !u || !y || u == y) return LGP_E_ARG;
+    LGP_ONE_THREAD();
     hipStream_t s = (hipStream_t)stream;
     switch (prec) {
         case LGP_F64: return matvec_f64(p->P, (const double*)u, (double*)y, s);
@@ -260,6 +286,7 @@ lgp_status lgp_factor_M_dir(lgp_problem p, const int* Ta_dir, int Tb, lgp_dtype 
     *out = nullptr;
     if (!p || !buf || !valid_truncations(p->P, Ta_dir, Tb)) return LGP_E_ARG;
     if (buf_bytes < lgp_factor_bytes_dir(p, Ta_dir, Tb, store)) return LGP_E_NOMEM;
+    LGP_ONE_THREAD();
     Problem& P = p->P;
     hipStream_t s = (hipStream_t)stream;
     lgp_factor_s* hF = new (std::nothrow) lgp_factor_s();
@@ -423,6 +450,7 @@ lgp_status lgp_factor_const(lgp_problem p, void* buf, size_t buf_bytes, void* st
     *out = nullptr;
     if (!p || !buf) return LGP_E_ARG;
     if (buf_bytes < lgp_factor_const_bytes(p)) return LGP_E_NOMEM;
+    LGP_ONE_THREAD();
     if (p->P.d == 1) return lgp_factor_M(p, 0, 0, LGP_F64, buf, buf_bytes, stream, out);
     lgp_factor_s* hF = new (std::nothrow) lgp_factor_s();
     if (!hF) return LGP_E_NOMEM;
@@ -439,17 +467,20 @@ lgp_status lgp_factor_const(lgp_problem p, void* buf, size_t buf_bytes, void* st
 lgp_status lgp_ilu_forward(lgp_factor m, const double* r, double* y, void* stream) {
     if (!m || !r || !y || r == y) return LGP_E_ARG;
     if (m->F.kind != 0) return LGP_E_UNSUPPORTED;
+    LGP_ONE_THREAD();
     return sweep(m->F, false, r, y, (hipStream_t)stream);
 }
 
 lgp_status lgp_ilu_backward(lgp_factor m, const double* y, double* z, void* stream) {
     if (!m || !y || !z || y == z) return LGP_E_ARG;
     if (m->F.kind != 0) return LGP_E_UNSUPPORTED;
+    LGP_ONE_THREAD();
     return sweep(m->F, true, y, z, (hipStream_t)stream);
 }
 
 lgp_status lgp_precond_apply(lgp_factor m, const double* r, double* z, void* stream) {
     if (!m || !r || !z || r == z) return LGP_E_ARG;
+    LGP_ONE_THREAD();
     if (m->F.kind == 1) return const_apply(m->F, r, z, (hipStream_t)stream);
     lgp_status st = sweep(m->F, false, r, m->F.y_tmp, (hipStream_t)stream);
     if (st != LGP_OK) return st;
@@ -487,6 +518,7 @@ lgp_status lgp_pcg_solve(lgp_problem p, lgp_factor m, const double* F, double* x
                          void* ws, size_t ws_bytes, void* stream, lgp_solve_info* info) {
     if (!p || !m || !F || !x || !ws || !info) return LGP_E_ARG;
     if (m->F.P != &p->P) return LGP_E_ARG;
+    LGP_ONE_THREAD();
     lgp_solve_opts o;
     o.rtol = 1e-10;
     o.max_iter = 2000;

@@ -1533,30 +1533,7 @@ struct FactorHostTables {
 
 static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& H, hipEvent_t* ev);
 
-// One non-blocking stream per device, at the default priority, for work the
-// library overlaps with the caller's stream; created on first use and kept
-// for the life of the process.
-hipStream_t side_stream() {
-    static std::mutex mu;
-    static std::map<int, hipStream_t> streams;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = streams.find(dev);
-    if (it != streams.end()) return it->second;
-    hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    streams[dev] = st;
-    return st;
-}
-
-void factor_release(Factor& F) {
-    if (F.ut_ready) {
-        hipEventSynchronize(F.ut_ready);   // the side stream may still write Ut
-        hipEventDestroy(F.ut_ready);
-        F.ut_ready = nullptr;
-    }
-}
+void factor_release(Factor& F) { (void)F; }
 
 lgp_status factor_build(Factor& F, hipStream_t s) {
     FactorHostTables H;
@@ -1814,36 +1791,23 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
         hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n, (const double*)F.invD, F.invD32);
     }
     LGP_CHECK_LAUNCH();
-    // The backward operator Ut is built on the library's side stream, after
-    // everything above: a solve's first forward substitution (which leaves
-    // most of the GPU idle) overlaps it, and backward substitutions wait for
-    // F.ut_ready. Reads of L (entries < n_lower) do not meet the padding
-    // writes above.
-    hipStream_t side = side_stream();
-    if (!side) return LGP_E_HIP;
-    if (!F.ut_ready) LGP_HIP(hipEventCreateWithFlags(&F.ut_ready, hipEventDisableTiming));
-    hipEvent_t e0 = nullptr;
-    LGP_HIP(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
-    LGP_HIP(hipEventRecord(e0, s));
-    const hipError_t werr = hipStreamWaitEvent(side, e0, 0);
-    hipEventDestroy(e0);
-    if (werr != hipSuccess) return LGP_E_HIP;
+    // The backward operator Ut, on the caller's stream after the factor
+    // (reads of L, entries < n_lower, do not meet the padding writes above).
     if (tiled) {
         const size_t shmem = (size_t)(R + maxspan) * maxK * 8;
         hipFuncSetAttribute((const void*)build_ut_tiled_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)shmem);
-        hipLaunchKernelGGL(build_ut_tiled_kernel, dim3((unsigned)((n + R - 1) / R), F.nruns), dim3(256), shmem, side,
+        hipLaunchKernelGGL(build_ut_tiled_kernel, dim3((unsigned)((n + R - 1) / R), F.nruns), dim3(256), shmem, s,
                            d, n1, n, F.ldl, (const int4*)F.d_offs, (const int4*)F.runs, R, (const double*)F.L, F.Ut);
     } else {
-        hipLaunchKernelGGL(build_ut_kernel, dim3(4096), dim3(256), 0, side, d, n1, n, F.nlo, F.ldl,
+        hipLaunchKernelGGL(build_ut_kernel, dim3(4096), dim3(256), 0, s, d, n1, n, F.nlo, F.ldl,
                            (const int4*)F.d_offs, (const double*)F.L, F.Ut);
     }
-    hipLaunchKernelGGL(zero_pad_kernel, dim3(4096), dim3(256), 0, side, n, F.ldl, F.nlo, F.Ut);
+    hipLaunchKernelGGL(zero_pad_kernel, dim3(4096), dim3(256), 0, s, n, F.ldl, F.nlo, F.Ut);
     if (F.has32)
-        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, side, (int64_t)n * F.ldl, (const double*)F.Ut,
+        hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, s, (int64_t)n * F.ldl, (const double*)F.Ut,
                            F.Ut32);
     LGP_CHECK_LAUNCH();
-    LGP_HIP(hipEventRecord(F.ut_ready, side));
     return LGP_OK;
 }
 
@@ -1922,7 +1886,6 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
 
 lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStream_t s, const int* stop) {
     if (F.d == 1) return band1d_sweep<double>(F, backward, F.L, F.invD, in, out, s, stop);
-    if (backward && F.ut_ready) LGP_HIP(hipStreamWaitEvent(s, F.ut_ready, 0));
     return backward ? sweep_t<double>(F, true, F.Ut, F.invD, in, out, s, stop)
                     : sweep_t<double>(F, false, F.L, nullptr, in, out, s, stop);
 }
@@ -1930,7 +1893,6 @@ lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStr
 lgp_status sweep32(Factor& F, bool backward, const float* in, float* out, hipStream_t s, const int* stop) {
     if (!F.has32) return LGP_E_ARG;
     if (F.d == 1) return band1d_sweep<float>(F, backward, F.L32, F.invD32, in, out, s, stop);
-    if (backward && F.ut_ready) LGP_HIP(hipStreamWaitEvent(s, F.ut_ready, 0));
     return backward ? sweep_t<float>(F, true, F.Ut32, F.invD32, in, out, s, stop)
                     : sweep_t<float>(F, false, F.L32, nullptr, in, out, s, stop);
 }

@@ -305,6 +305,12 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
     if ((st = norm2_into(F, n, S, o.rtol, s)) != LGP_OK) return st;
     if ((st = read_state(S, s, h)) != LGP_OK) return st;
     const double normF = sqrt(h.sc[SC_FF]);
+    // a NaN or an infinity in F makes ||F|| non-finite: the stop rule of
+    // Alg. 1 can never be met, so the request is rejected
+    if (!std::isfinite(normF)) {
+        info->status = LGP_E_ARG;
+        return LGP_E_ARG;
+    }
     if (!(normF > 0.0)) {
         // F = 0: x = 0 is the solution
         LGP_HIP(hipMemsetAsync(x, 0, n * 8, s));
@@ -336,6 +342,12 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
 
     double relres = 0.0;
     if ((st = true_residual(&relres)) != LGP_OK) return st;
+    // a non-finite initial guess gives a non-finite residual
+    if (!std::isfinite(relres)) {
+        info->relres_true = relres;
+        info->status = LGP_E_ARG;
+        return LGP_E_ARG;
+    }
     const int check_every = o.check_every > 0 ? o.check_every : 4;
 
     if (!mixed) {
@@ -374,6 +386,10 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
         info->iters = total;
         info->outer = restarts;
         info->relres_true = relres;
+        if (!std::isfinite(relres)) {
+            info->status = LGP_E_BREAKDOWN;
+            return LGP_E_BREAKDOWN;
+        }
         if (relres > o.rtol) {
             info->status = LGP_E_NOCONV;
             return LGP_E_NOCONV;
@@ -418,6 +434,10 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
     info->iters = total;
     info->outer = outer;
     info->relres_true = relres;
+    if (!std::isfinite(relres)) {
+        info->status = LGP_E_BREAKDOWN;
+        return LGP_E_BREAKDOWN;
+    }
     if (relres > o.rtol) {
         info->status = LGP_E_NOCONV;
         return LGP_E_NOCONV;

@@ -29,6 +29,20 @@ extern thread_local int g_last_hip_error;
         }                                                               \
     } while (0)
 
+// At most one host thread at a time may be inside an entry point that
+// enqueues device work; a call from a second thread while another thread is
+// inside returns LGP_E_UNSUPPORTED. Nested calls on the owning thread pass.
+struct ThreadGuard {
+    bool ok;
+    ThreadGuard();
+    ~ThreadGuard();
+    ThreadGuard(const ThreadGuard&) = delete;
+    ThreadGuard& operator=(const ThreadGuard&) = delete;
+};
+#define LGP_ONE_THREAD()                                                \
+    ::lgp::ThreadGuard lgp_guard_;                                      \
+    if (!lgp_guard_.ok) return LGP_E_UNSUPPORTED
+
 // Bump allocator over a caller-provided device buffer (256-byte aligned
 // sub-buffers). Used twice: once with base == nullptr to size, once to carve.
 struct Carver {
@@ -134,7 +148,6 @@ struct Factor {
     // kind 1: the constant-coefficient operator solved exactly (matrix
     // diagonalisation); only P, d, n1, n and the cc* fields are used
     int kind = 0;
-    hipEvent_t ut_ready = nullptr;   // Ut (and its FP32 copy) complete on the library's side stream
     double* ccE = nullptr;     // [n1][n1] generalized eigenvectors, E^T S E = I, E^T M E = diag(lam)
     double* ccLam = nullptr;   // [n1]
     double* ccInv = nullptr;   // [n1^d] 1 / eigenvalues of the transformed operator
@@ -148,7 +161,6 @@ struct Factor {
 
 size_t plan_factor(Factor& F, void* buf, bool with32);
 lgp_status factor_build(Factor& F, hipStream_t s);
-hipStream_t side_stream();
 void factor_release(Factor& F);
 size_t const_factor_bytes(const Problem& P);
 lgp_status const_factor_build(Factor& F, Problem& P, void* buf, size_t bytes, hipStream_t s);

@@ -13,6 +13,7 @@ import synth
 from oracle import galerkin as gk
 from oracle import ilu as oilu
 from oracle import precond as pc
+from tests.checks import assert_entrywise, matvec_magnitude
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +44,7 @@ def test_edge_factor_sweeps_and_solve(d, N, Ta, Tb):
     # product
     u = synth.random_vector(n, 9)
     ref = gk.matvec_sumfact(d, N, a, b, u, B)
-    assert np.linalg.norm(_host(P.matvec(_dev(u))) - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert_entrywise(_host(P.matvec(_dev(u))), ref, 1e-12, matvec_magnitude(d, N, a, b, u, B), "matvec")
     # factor against the oracle's stencil ILU(0)
     ah, bh = pc.series_pair(a, b, B, Ta, Tb)
     offs = pc.stencil_offsets(ah, bh)
@@ -56,8 +57,9 @@ def test_edge_factor_sweeps_and_solve(d, N, Ta, Tb):
     assert np.max(np.abs(_host(desc["L"]) - Lo)) <= 1e-12 * max(1.0, np.max(np.abs(Lo)))
     assert np.max(np.abs(_host(desc["D"]) - Do)) <= 1e-12 * np.max(np.abs(Do))
     r = synth.random_vector(n, 10)
-    z = _host(M.apply(_dev(r)))
-    assert np.linalg.norm(z - st.apply(r)) <= 1e-12 * np.linalg.norm(st.apply(r))
+    assert_entrywise(_host(M.forward(_dev(r))), st.forward(r), 1e-12, label="forward")
+    assert_entrywise(_host(M.backward(_dev(r))), st.backward(r), 1e-12, label="backward")
+    assert_entrywise(_host(M.apply(_dev(r))), st.apply(r), 1e-12, label="apply")
     # solve
     F = _dev(synth.random_vector(n, 11))
     x, info = pcg_solve(P, M, F, rtol=1e-10)

@@ -9,7 +9,9 @@ plus corner, edge and centre rows). The substitutions are checked by their
 residuals at sampled rows, the operator and the load vector elementwise over
 the whole grid, and the solutions by the oracle's own FP64 residual.
 
-Tolerances: matvec and load vector relative 1e-12 (2-norm); ILU(0)
+Tolerances: matvec entry by entry within 1e-12 of each entry's term
+magnitude, and relative 1e-12 (2-norm; 2D: against extended precision);
+load vector relative 1e-12 (2-norm); ILU(0)
 equations 1e-12 relative to the sum of the magnitudes of the terms on both
 sides (those of L D L^T and those of the Kronecker sum that gives M), plus
 an absolute rounding of 1e-14 * max|c| in each truncated series
@@ -28,6 +30,7 @@ import synth
 from oracle import galerkin as gk
 from oracle import precond as pc
 from oracle import workload as owl
+from tests.checks import assert_entrywise, load_magnitude, matvec_magnitude
 
 pytestmark = pytest.mark.gpu
 
@@ -169,6 +172,10 @@ def test_fullsize_load_vector_and_matvec(ci, golden_dir):
     y = _host(C.P.matvec(_dev(u)))
     ref = C.matvec_oracle(u)
     rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    # every entry within 1e-12 of the magnitude of its terms
+    mag = matvec_magnitude(C.d, C.N, C.a_o, C.b_o, u, C.B)
+    worst = assert_entrywise(y, ref, 1e-12, mag, "matvec")
+    print("%s matvec: worst entry %.2e of its term magnitude" % (ci, worst))
     if ci == "2d_N1024_T8":
         meta, rows, vals = _golden_matvec(os.path.join(golden_dir, "matvec_ext_2d_N1024.txt"))
         err = np.max(np.abs(y[rows] - vals)) / meta["norminf"]
@@ -180,46 +187,48 @@ def test_fullsize_load_vector_and_matvec(ci, golden_dir):
         assert rel <= 1e-12
 
 
-@pytest.mark.parametrize("ci,count", [("2d_N1024_T8", 48), ("3d_N128_T6", 6)])
+@pytest.mark.parametrize("ci,count", [("2d_N1024_T8", 200), ("3d_N128_T6", 200)])
 def test_fullsize_ilu0_equations(ci, count):
     """Sec. 4.3: (L D L^T)(i, i+d_k) = M(i, i+d_k) for every lower offset k
-    and the diagonal, at sampled rows i."""
+    and the diagonal, at sampled rows i. The entries of L the equations need
+    are gathered on the device (torch indexing); the sums are formed in FP64."""
     C = _case(ci)
     assert [tuple(o[:C.d]) for o in C.desc["offsets"]] == [tuple(o) for o in C.offs]
     ks, ls, ms = C.pair_table()
     nlo = C.nlo
     lower = C.offs[:nlo]
+    dev = C.desc["L"].device
+    Lv, Dv = C.desc["L"], C.desc["D"]
+    ks_t, ls_t, ms_t = (torch.from_numpy(v).to(dev) for v in (ks, ls, ms))
     # each side computes the truncated series itself (an FDLT over the q^d
     # nodes): allow each series coefficient an absolute rounding of
     # 1e-14 * max|coefficient|
     cerr = 1e-14 * max(np.max(np.abs(C.ah)), np.max(np.abs(C.bh)))
+    rows = C.sample_rows(count, 1000 + C.cfg.seed)
+    Me_all, Mmag_all, Pmag_all = pc.M_rows_entries(C.d, C.n1, C.ah, C.bh, rows,
+                                                   list(lower) + [tuple([0] * C.d)], C.S, C.Mm)
+    print("%s: oracle M entries for %d rows" % (ci, len(rows)), flush=True)
     worst = 0.0
-    for i in C.sample_rows(count, 1000 + C.cfg.seed):
-        nb = [C.shifted(i, o) for o in lower]              # rows i + d_k
-        need = [i] + [r for r in nb if r >= 0]
-        Lr, Dr = _rows_of(C, need)
-        pos = {r: t for t, r in enumerate(need)}
-        Li = Lr[0]
-        Dn = np.array([Dr[pos[r]] if r >= 0 else 0.0 for r in nb])     # D(i + d_l)
-        Me, Mmag, Pmag = pc.M_row_entries(C.d, C.n1, C.ah, C.bh, i, list(lower) + [tuple([0] * C.d)], C.S, C.Mm,
-                                    return_abs=True)
+    for t, i in enumerate(rows):
+        nb = np.array([C.shifted(i, o) for o in lower])              # rows i + d_k
+        valid_k = nb >= 0
+        nb_t = torch.from_numpy(nb).to(dev)
+        ok_t = (nb_t >= 0).to(torch.float64)
+        nbc = nb_t.clamp(min=0)
+        Li_t = Lv[i].to(torch.float64)
+        Dn_t = Dv[nbc] * ok_t                                         # D(i + d_l)
+        vals = Lv[nbc[ks_t], ms_t] * ok_t[ks_t]                       # L(i + d_k, i + d_l)
+        terms = Li_t[ls_t] * Dn_t[ls_t] * vals
+        lhs_t = torch.zeros(nlo, dtype=torch.float64, device=dev).index_add_(0, ks_t, terms)
+        mag_t = torch.zeros(nlo, dtype=torch.float64, device=dev).index_add_(0, ks_t, terms.abs())
+        Li, Dn, lhs, mag = (_host(v) for v in (Li_t, Dn_t, lhs_t, mag_t))
+        Di = float(_host(Dv[i]))
+        Me, Mmag, Pmag = Me_all[t], Mmag_all[t], Pmag_all[t]
         # entries of L outside the grid are stored as zero
-        for k in range(nlo):
-            if nb[k] < 0:
-                assert Li[k] == 0.0
+        assert np.all(Li[~valid_k] == 0.0), i
         # off-diagonal equations
-        lhs = np.zeros(nlo)
-        mag = np.zeros(nlo)
-        valid_k = np.array([r >= 0 for r in nb])
-        Lnb = np.zeros((nlo, nlo))
-        for k in range(nlo):
-            if nb[k] >= 0:
-                Lnb[k] = Lr[pos[nb[k]]]
-        terms = Li[ls] * Dn[ls] * Lnb[ks, ms]
-        np.add.at(lhs, ks, terms)
-        np.add.at(mag, ks, np.abs(terms))
-        lhs += Li * Dn
-        mag += np.abs(Li * Dn)
+        lhs = lhs + Li * Dn
+        mag = mag + np.abs(Li * Dn)
         err = np.abs(lhs - Me[:nlo])[valid_k]
         allow = (1e-12 * (mag + Mmag[:nlo]) + cerr * Pmag[:nlo])[valid_k] + 1e-300
         if err.size:
@@ -227,35 +236,42 @@ def test_fullsize_ilu0_equations(ci, count):
             worst = max(worst, float(np.max(err / allow)))
         # diagonal
         dterms = Li * Li * Dn
-        dl = dterms.sum() + Dr[0]
-        assert abs(dl - Me[nlo]) <= 1e-12 * (np.abs(dterms).sum() + abs(Dr[0]) + Mmag[nlo]) + cerr * Pmag[nlo], i
-    print("ILU(0) equations: worst residual / allowance %.2e" % worst)
+        dl = dterms.sum() + Di
+        assert abs(dl - Me[nlo]) <= 1e-12 * (np.abs(dterms).sum() + abs(Di) + Mmag[nlo]) + cerr * Pmag[nlo], i
+        if (t + 1) % 25 == 0:
+            print("  %d/%d rows, worst residual / allowance %.2e" % (t + 1, len(rows), worst), flush=True)
+    print("ILU(0) equations: worst residual / allowance %.2e over %d rows" % (worst, len(rows)))
 
 
-@pytest.mark.parametrize("ci,count", [("2d_N1024_T8", 256), ("3d_N128_T6", 16)])
+@pytest.mark.parametrize("ci,count", [("2d_N1024_T8", 256), ("3d_N128_T6", 200)])
 def test_fullsize_sweeps(ci, count):
     """Alg. 3 and Alg. 4 at sampled rows: r_i = y_i + sum_k L(i,k) y(i+d_k) and
-    y_i / D(i) = z_i + sum_k L(i-d_k, k) z(i-d_k)."""
+    y_i / D(i) = z_i + sum_k L(i-d_k, k) z(i-d_k). Entries of L gathered on
+    the device."""
     C = _case(ci)
     r = synth.random_vector(C.n, 500 + C.cfg.seed)
     y = _host(C.M.forward(_dev(r)))
     z = _host(C.M.backward(_dev(y)))
     lower = C.offs[:C.nlo]
+    dev = C.desc["L"].device
+    Lv, Dv = C.desc["L"], C.desc["D"]
     rows = C.sample_rows(count, 2000 + C.cfg.seed)
-    Lr, Dr = _rows_of(C, rows)
     for t, i in enumerate(rows):
         nb = np.array([C.shifted(i, o) for o in lower])
         ok = nb >= 0
-        terms = Lr[t][ok] * y[nb[ok]]
+        Li = _host(Lv[i])
+        terms = Li[ok] * y[nb[ok]]
         res = r[i] - y[i] - terms.sum()
         assert abs(res) <= 1e-12 * (abs(r[i]) + np.abs(terms).sum()), ("forward", i, res)
         up = np.array([C.shifted(i, tuple(-x for x in o)) for o in lower])      # rows i - d_k
-        oku = up >= 0
-        kk = np.nonzero(oku)[0]
-        Lu, _ = _rows_of(C, [int(x) for x in up[oku]]) if len(kk) else (np.zeros((0, C.nlo)), None)
-        terms_b = Lu[np.arange(len(kk)), kk] * z[up[oku]]
-        res_b = y[i] / Dr[t] - z[i] - terms_b.sum()
-        assert abs(res_b) <= 1e-12 * (abs(y[i] / Dr[t]) + np.abs(terms_b).sum()), ("backward", i, res_b)
+        kk = np.nonzero(up >= 0)[0]
+        Lu = _host(Lv[torch.from_numpy(up[kk]).to(dev), torch.from_numpy(kk).to(dev)]) if len(kk) else np.zeros(0)
+        terms_b = Lu * z[up[kk]]
+        Di = float(_host(Dv[i]))
+        res_b = y[i] / Di - z[i] - terms_b.sum()
+        assert abs(res_b) <= 1e-12 * (abs(y[i] / Di) + np.abs(terms_b).sum()), ("backward", i, res_b)
+        if (t + 1) % 50 == 0:
+            print("  %d/%d rows" % (t + 1, len(rows)), flush=True)
 
 
 @pytest.mark.parametrize("ci", ["2d_N1024_T8", "3d_N128_T6"])

@@ -255,3 +255,28 @@ def test_1d_constant_preconditioner_is_t0_band_factor():
     z2 = pc.constant_solve(1, N, ca, cb, r)
     assert np.linalg.norm(z1 - z2) <= 1e-11 * np.linalg.norm(z2)
     assert np.linalg.norm(pc.constant_apply(1, N, ca, cb, z1) - r) <= 1e-12 * np.linalg.norm(r)
+
+
+@pytest.mark.parametrize("d,N,T,seed", [(2, 20, 4, 0), (3, 11, 3, 2), (3, 9, 6, 1)])
+def test_many_rows_entries_match_row_by_row(d, N, T, seed):
+    """The many-rows form of M's entries equals the row-by-row form (same
+    terms, another multiplication order) on sampled rows, inside and at the
+    grid's faces."""
+    import synth
+    from oracle import galerkin as gk
+    from oracle import precond as pc
+    from oracle import workload as owl
+    B = gk.Basis(N)
+    c = synth.coefficient_draws(d, 6, seed)
+    ah, bh = pc.series_pair(owl.coefficient_a(c, B.x), owl.coefficient_b(d, B.x), B, T, T)
+    offs = pc.stencil_offsets(ah, bh)
+    S, Mm = pc.band_factors(N - 1, T)
+    n = (N - 1) ** d
+    rows = [0, 1, n - 1, n // 2, n // 3, N - 2]
+    out, mag, pmag = pc.M_rows_entries(d, N - 1, ah, bh, rows, offs, S, Mm)
+    for t, r in enumerate(rows):
+        o1, m1, p1 = pc.M_row_entries(d, N - 1, ah, bh, r, offs, S, Mm, return_abs=True)
+        scale = max(np.max(m1), 1e-300)
+        assert np.max(np.abs(out[t] - o1)) <= 1e-14 * scale
+        assert np.max(np.abs(mag[t] - m1)) <= 1e-14 * scale
+        assert np.max(np.abs(pmag[t] - p1)) <= 1e-14 * max(np.max(p1), 1e-300)
