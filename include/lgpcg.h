@@ -240,6 +240,22 @@ lgp_status lgp_pcg_solve(lgp_problem p, lgp_factor m, const double* F, double* x
                          const lgp_solve_opts* opts, void* ws, size_t ws_bytes,
                          void* stream, lgp_solve_info* info);
 
+/* ------------------------------------------------ allocation-free solve -- */
+/* For callers that cannot allocate device memory at solve time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * lgp_pcg_solve without the workspace argument. The PCG workspace is a
+ * device array inside the library, one copy per GPU, of
+ * lgp_pcg_solve_noalloc_max_bytes() bytes (64 MiB), held until the process
+ * ends. Problems whose workspace (lgp_solve_workspace_bytes) exceeds it are
+ * refused with LGP_E_NOMEM: FP64 solves up to about 2.09e6 unknowns, mixed
+ * ones up to about 1.19e6. The call itself allocates nothing. Every call on
+ * a GPU uses that GPU's one array: calls that overlap in time on one GPU
+ * (from any stream) race and must not be issued. Arguments, errors and
+ * synchronisation otherwise as lgp_pcg_solve. */
+size_t lgp_pcg_solve_noalloc_max_bytes(void);
+lgp_status lgp_pcg_solve_noalloc(lgp_problem p, lgp_factor m, const double* F, double* x,
+                                 const lgp_solve_opts* opts, void* stream, lgp_solve_info* info);
+
 #ifdef __cplusplus
 }
 #endif

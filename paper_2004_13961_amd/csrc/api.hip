@@ -2,6 +2,7 @@
 // include/lgpcg.h).
 #include <algorithm>
 #include <array>
+#include <map>
 #include <cmath>
 #include <mutex>
 #include <new>
@@ -540,6 +541,52 @@ lgp_status lgp_pcg_solve(lgp_problem p, lgp_factor m, const double* F, double* x
     lgp_status st = pcg_solve_impl(p->P, m->F, F, x, o, ws, ws_bytes, (hipStream_t)stream, info);
     info->status = st;
     return st;
+}
+
+
+// ------------------------------------------------- allocation-free solve --
+// Workspace of lgp_pcg_solve_noalloc: one file-scope device array, one copy
+// per GPU, shared by every call on that GPU.
+static __device__ __align__(256) unsigned char scratch[LGP_NOALLOC_SCRATCH_BYTES];
+
+// Device address of this GPU's copy of `scratch`, taken once per device with
+// that device current (host code never passes the array's name itself).
+static lgp_status noalloc_scratch(void** out) {
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    int dev = 0;
+    LGP_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void* ptr = nullptr;
+        LGP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return LGP_E_HIP;
+        it = addr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return LGP_OK;
+}
+
+size_t lgp_pcg_solve_noalloc_max_bytes(void) { return (size_t)LGP_NOALLOC_SCRATCH_BYTES; }
+
+lgp_status lgp_pcg_solve_noalloc(lgp_problem p, lgp_factor m, const double* F, double* x,
+                                 const lgp_solve_opts* opts, void* stream, lgp_solve_info* info) {
+    if (!p || !m || !F || !x || !info) return LGP_E_ARG;
+    const size_t need = lgp_solve_workspace_bytes(p, opts ? opts->inner : LGP_F64);
+    if (need == 0 || need > (size_t)LGP_NOALLOC_SCRATCH_BYTES) {
+        info->status = LGP_E_NOMEM;
+        return LGP_E_NOMEM;
+    }
+    void* ws = nullptr;
+    {
+        LGP_ONE_THREAD();
+        lgp_status st = noalloc_scratch(&ws);
+        if (st != LGP_OK) return st;
+    }
+    // the solver sets every workspace entry it reads before reading it, so
+    // what an earlier call left in the array does not matter
+    return lgp_pcg_solve(p, m, F, x, opts, ws, (size_t)LGP_NOALLOC_SCRATCH_BYTES, stream, info);
 }
 
 }  // extern "C"

@@ -11,6 +11,10 @@ namespace lgp {
 
 extern thread_local int g_last_hip_error;
 
+// Size of the device array that serves as the workspace of
+// lgp_pcg_solve_noalloc (one copy per GPU).
+#define LGP_NOALLOC_SCRATCH_BYTES (64u << 20)
+
 #define LGP_HIP(call)                                                   \
     do {                                                                \
         hipError_t e_ = (call);                                         \

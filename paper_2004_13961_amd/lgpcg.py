@@ -30,6 +30,7 @@ EXPORTS = [
     "lgp_destroy_factor",
     "lgp_precond_apply", "lgp_ilu_forward", "lgp_ilu_backward", "lgp_factor_describe",
     "lgp_solve_workspace_bytes", "lgp_pcg_solve", "lgp_factor_const_bytes", "lgp_factor_const",
+    "lgp_pcg_solve_noalloc_max_bytes", "lgp_pcg_solve_noalloc",
 ]
 
 
@@ -96,6 +97,8 @@ def lib():
         "lgp_solve_workspace_bytes": (sz, [vp, i32]),
         "lgp_pcg_solve": (i32, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts), vp, sz, vp,
                                 ctypes.POINTER(SolveInfo)]),
+        "lgp_pcg_solve_noalloc_max_bytes": (sz, []),
+        "lgp_pcg_solve_noalloc": (i32, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
