@@ -1,24 +1,29 @@
 """Benchmark: preconditioned Legendre-Galerkin PCG on one MI355X.
 
-Workload (default): 2D, N = 1024 ((N-1)^2 = 1,046,529 unknowns), coefficient
-a = 2 + sum_{j,k<=12} c_jk L_j(x) L_k(y) (c_jk = 0.3 2^-(j+k) U(-1,1), seed 1),
-b = 1 + x^2 + y^2, f from the manufactured u* = sin(pi x) sin(pi y) e^{x+y},
-preconditioner truncation T = 8, FP64, PCG from x0 = 0 to relative residual
-1e-10. Inputs (nodal a, b, f) are resident in HBM before timing starts.
+Default workload `3d_N256_T6_mixed` (the largest single-GPU configuration):
+3D, N = 256 (255^3 = 16,581,375 unknowns), a = 2 + sum_{j,k,l<=6} c_jkl
+L_j L_k L_l (c = 0.3 2^-(j+k+l) U(-1,1), seed 3), b = 1 + |x|^2, f from the
+manufactured u* = prod sin(pi x_i) e^{x_i}, preconditioner truncation T = 6
+with the ILU(0) factorisation in FP64 and the factor kept in FP32 only (the
+FP64 factor, 306 GB, does not fit in HBM), mixed-precision solve: FP32 inner
+PCG (products on the matrix cores, inner tolerance 1e-4) inside FP64
+iterative refinement to a true relative residual of 1e-10. Other workloads:
+--workload 2d_N32_T4 | 2d_N1024_T8 | 3d_N128_T6 (FP64).
 
-One timed step = one request end to end on the device: build the operator
-from the nodal coefficients, assemble and factor the preconditioner
-(ILU(0) in FP64), form the load vector, and run PCG to 1e-10 (true FP64
-residual checked). `value` is steps per second. Also reported: solve-only
-rate (factors built), the FP64 matvec rate against the matrix-core peak, the
-forward-sweep bandwidth, mixed-precision (FP32 and BF16 inner) solves, and the
-oracle on the host CPU (bounded sample).
+One timed step = one request end to end on the device, inputs (nodal a, b,
+f) resident in HBM: build the operator, assemble and factor the
+preconditioner, form the load vector, solve (true FP64 residual checked).
+`value` is requests per second. Also reported: solve-only rates (FP64 and /
+or FP32 and BF16 inner), matvec TFLOP/s in FP64, FP32 and BF16 against the
+matrix-core peaks, substitution bandwidth, the dominant kernel's roofline,
+and the oracle on the host CPU (bounded sample).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2d_N1024_T8]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,94 +35,198 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
-
-
-def matvec_flops(d, N):
-    n1, q = N - 1, N + 1
-    if d == 2:
-        return 8.0 * n1 * n1 * q + 12.0 * q * q * n1
-    return 8.0 * q * n1 ** 3 + 12.0 * q * q * n1 * n1 + 16.0 * q ** 3 * n1
-
-
-def nnz_lower(d, n1, offsets):
-    """In-grid strictly lower entries of L: sum over lower offsets of the
-    number of rows whose column stays in the grid."""
-    tot = 0
-    for o in offsets:
-        key = tuple(reversed(o[:d]))
-        if key < tuple([0] * d):
-            cnt = 1
-            for k in range(d):
-                cnt *= max(0, n1 - abs(o[k]))
-            tot += cnt
-    return tot
-
-
-def cpu_baseline(cfg, sample_rows):
-    """The oracle (plain FP64 numpy + single-threaded C) timed on the same
-    workload, as a bounded sample: coefficient series, 1D factors and the
-    stencil rows of M in full; Alg. 2 on the first `sample_rows` rows (rows
-    depend only on earlier rows, so the prefix costs what it costs inside the
-    full factorisation), scaled to all rows; one PCG iteration (sum-factorised
-    matvec + both substitutions with the prefix-factored rows completed by
-    the sample scaling), scaled to the iteration count of the GPU solve."""
-    import synth
-    from oracle import galerkin as gk
-    from oracle import ilu as oilu
-    from oracle import pcg as opcg
-    from oracle import precond as pc
-    from oracle import workload as owl
-    t0 = time.perf_counter()
-    B = gk.Basis(cfg.N)
-    c = synth.coefficient_draws(cfg.d, cfg.J, cfg.seed)
-    a = owl.coefficient_a(c, B.x)
-    b = owl.coefficient_b(cfg.d, B.x)
-    F = gk.load_vector(cfg.d, cfg.N, owl.rhs_f(c, B.x), B)
-    ah, bh = pc.series_pair(a, b, B, cfg.T, cfg.T)
-    offs = pc.stencil_offsets(ah, bh)
-    H = pc.stencil_rows(cfg.d, cfg.n1, ah, bh, offs)
-    t_rows = time.perf_counter() - t0
-    st = oilu.StencilILU(cfg.d, cfg.n1, offs, H)
-    rows = min(sample_rows, cfg.n)
-    t1 = time.perf_counter()
-    st.factor(nrows=rows)
-    t_fac = (time.perf_counter() - t1) * (cfg.n / rows)
-    mv = lambda v: gk.matvec_sumfact(cfg.d, cfg.N, a, b, v, B)
-    t1 = time.perf_counter()
-    z = st.apply(F)
-    w = mv(z)
-    t_it = time.perf_counter() - t1
-    sample = ("oracle on %s: operator data + stencil rows %.1f s (full), Alg. 2 on %d of %d rows "
-              "scaled to %.1f s, one PCG iteration (matvec + Alg. 3 + Alg. 4) %.2f s"
-              % (cfg.name, t_rows, rows, cfg.n, t_fac, t_it))
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    return dict(setup=t_rows + t_fac, t_iter=t_it, sample=sample, threads=threads)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense matrix-core peaks
+FP64_VECTOR_TFLOPS = 78.6
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = {"factor": "paper_2004_13961_amd/csrc/ilu.hip", "sweep": "paper_2004_13961_amd/csrc/ilu.hip",
-                  "matvec": "paper_2004_13961_amd/csrc/gemm.hip"}
+def matvec_flops(d, N):
+    n1, q = N - 1, N + 1
+    if d == 1:
+        return 4.0 * n1 * q
+    if d == 2:
+        return 8.0 * n1 * n1 * q + 12.0 * q * q * n1
+    return 8.0 * q * n1 ** 3 + 12.0 * q * q * n1 * n1 + 16.0 * q ** 3 * n1
+
+
+def _range_count(n1, a, b, lo=0, hi=None):
+    """Number of x in [lo, hi) with x, x + a, x + b all in [0, n1) (arrays)."""
+    hi = n1 if hi is None else hi
+    start = np.maximum(lo, np.maximum(0, np.maximum(-a, -b)))
+    stop = np.minimum(hi, n1 - np.maximum(0, np.maximum(a, b)))
+    return np.maximum(0, stop - start)
+
+
+def lower_entries(d, n1, offsets):
+    """In-grid strictly lower entries of L (sum over lower offsets of the rows
+    whose column stays in the grid)."""
+    offs = np.array([list(o[:d]) + [0] * (3 - d) for o in offsets], dtype=np.int64)
+    lower = np.array([tuple(reversed(o[:d])) < tuple([0] * d) for o in offsets])
+    tot = np.ones(lower.sum(), dtype=np.float64)
+    for k in range(d):
+        tot *= _range_count(n1, offs[lower, k], 0 * offs[lower, k])
+    return float(tot.sum())
+
+
+def _offset_cube(offs):
+    """Membership of offset vectors in the pattern: a boolean cube over
+    [-2h, 2h]^3 (differences of two offsets stay inside)."""
+    h = int(np.abs(offs).max())
+    R = 2 * h
+    cube = np.zeros((2 * R + 1,) * 3, dtype=bool)
+    cube[offs[:, 2] + R, offs[:, 1] + R, offs[:, 0] + R] = True
+    return cube, R
+
+
+def _rows_count(d, n1, a, b, yrange, zrange):
+    c = np.ones(len(b))
+    for ax in range(d):
+        lo, hi = 0, n1
+        if ax == 1 and yrange is not None:
+            lo, hi = yrange
+        if ax == 2 and zrange is not None:
+            lo, hi = zrange
+        c *= _range_count(n1, np.full(len(b), a[ax]), b[:, ax], lo, hi)
+    return c
+
+
+def ilu_pairs(d, n1, offsets, yrange=None, zrange=None):
+    """Left-looking ILU(0) work: number of (row, j, l) with L(i, i+d_j) and
+    L(i+d_j, i+d_j+d_l) both in the grid, d_j and d_l lower, d_j + d_l in
+    the pattern (each such triple is one multiply-add of Alg. 2 with
+    U = D L^T). Optionally rows restricted to y, z ranges."""
+    offs = np.array([list(o[:d]) + [0] * (3 - d) for o in offsets], dtype=np.int64)
+    cube, R = _offset_cube(offs)
+    diag = [tuple(o) for o in offs.tolist()].index((0, 0, 0))
+    lower = offs[:diag]
+    tot = 0.0
+    for dj in lower:
+        dk = lower + dj                          # d_j + d_l for every lower l
+        inS = cube[dk[:, 2] + R, dk[:, 1] + R, dk[:, 0] + R]
+        if inS.any():
+            tot += _rows_count(d, n1, dj, dk[inS], yrange, zrange).sum()
+    return tot
+
+
+def oracle_c_work(d, n1, offsets, yrange=None, zrange=None):
+    """Inner-loop iterations of the oracle's Alg. 2 (C, IKJ order): per row,
+    per lower offset k in the grid, per later offset j with j - k in the
+    pattern and j in the grid."""
+    offs = np.array([list(o[:d]) + [0] * (3 - d) for o in offsets], dtype=np.int64)
+    cube, R = _offset_cube(offs)
+    diag = [tuple(o) for o in offs.tolist()].index((0, 0, 0))
+    tot = 0.0
+    for ok in range(diag):
+        a = offs[ok]
+        later = offs[ok + 1:]
+        df = later - a
+        inS = cube[df[:, 2] + R, df[:, 1] + R, df[:, 0] + R]
+        if inS.any():
+            tot += _rows_count(d, n1, a, later[inS], yrange, zrange).sum()
+    return tot
+
+
+def cpu_baseline(cfg, sample_lines, iters):
+    """The oracle (plain FP64 numpy + single-threaded C) on the same
+    workload, timed on a bounded sample of rows and scaled by the oracle's
+    own operation counts:
+      * stencil rows of M for the first z-plane (3D) or all rows (2D);
+      * Alg. 2 on the first `sample_lines` grid lines of rows, scaled to the
+        whole grid by the count of the C loop's inner iterations (rows near
+        the faces have fewer terms, so the count, not the row count, scales);
+      * Alg. 3 on the same rows, scaled by the in-grid entries of L; Alg. 4
+        taken equal to Alg. 3 (same entries, one division more per row);
+      * one sum-factorised FP64 matvec over the whole grid;
+    total = setup + factorisation + `iters` x (matvec + both substitutions)."""
+    import synth
+    from oracle import galerkin as gk
+    from oracle import ilu as oilu
+    from oracle import precond as pc
+    from oracle import workload as owl
+    d, N, n1 = cfg.d, cfg.N, cfg.N - 1
+    t0 = time.perf_counter()
+    B = gk.Basis(N)
+    c = synth.coefficient_draws(d, cfg.J, cfg.seed)
+    a = owl.coefficient_a(c, B.x)
+    b = owl.coefficient_b(d, B.x)
+    F = gk.load_vector(d, N, owl.rhs_f(c, B.x), B)
+    ah, bh = pc.series_pair(a, b, B, cfg.T, cfg.T)
+    offs = pc.stencil_offsets(ah, bh)
+    t_series = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    H = pc.stencil_rows(d, n1, ah, bh, offs, nplanes=1 if d == 3 else None)
+    t_rows = time.perf_counter() - t1
+    rows_in_H = H.shape[0]
+    t_rows_full = t_rows * (n1 ** d / rows_in_H)
+    lines = min(sample_lines, n1)
+    nrows = lines * n1
+    st = oilu.StencilILU(d, n1, offs, H)
+    t1 = time.perf_counter()
+    st.factor(nrows=nrows)
+    t_fac_s = time.perf_counter() - t1
+    yr = (0, lines)
+    zr = (0, 1) if d == 3 else None
+    w_s = oracle_c_work(d, n1, offs, yrange=yr, zrange=zr)
+    w_full = oracle_c_work(d, n1, offs)
+    t_fac = t_fac_s * (w_full / max(w_s, 1.0))
+    r = np.ascontiguousarray(F[:rows_in_H]) if d == 3 else F
+    t1 = time.perf_counter()
+    st.forward_prefix(r, nrows)
+    t_fw_s = time.perf_counter() - t1
+    e_s = lower_entries_prefix(d, n1, offs, lines)
+    e_full = lower_entries(d, n1, offs)
+    t_sweeps = 2.0 * t_fw_s * (e_full / max(e_s, 1.0))
+    u = np.random.default_rng(0).uniform(0.0, 1.0, size=n1 ** d)
+    t1 = time.perf_counter()
+    gk.matvec_sumfact(d, N, a, b, u, B)
+    t_mv = time.perf_counter() - t1
+    total = t_series + t_rows_full + t_fac + iters * (t_mv + t_sweeps)
+    sample = ("oracle on %s: series and offsets %.1f s; stencil rows of M for %d rows %.1f s, scaled to all rows "
+              "%.0f s; Alg. 2 on the first %d lines (%d rows) %.2f s, scaled by the C loop's inner iterations "
+              "(%.3g of %.3g) to %.0f s; Alg. 3 on those rows %.3f s, scaled by in-grid L entries and doubled for "
+              "Alg. 4: %.1f s per application; one full FP64 matvec %.2f s; total over %d iterations"
+              % (cfg.name, t_series, rows_in_H, t_rows, t_rows_full, lines, nrows, t_fac_s, w_s, w_full, t_fac,
+                 t_fw_s, t_sweeps, t_mv, iters))
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return dict(total=total, sample=sample, threads=threads)
+
+
+def lower_entries_prefix(d, n1, offsets, lines):
+    """In-grid lower entries of L in the rows of the first `lines` grid lines
+    (z = 0 plane in 3D)."""
+    offs = np.array([list(o[:d]) + [0] * (3 - d) for o in offsets], dtype=np.int64)
+    lower = np.array([tuple(reversed(o[:d])) < tuple([0] * d) for o in offsets])
+    lo = offs[lower]
+    tot = _range_count(n1, lo[:, 0], 0 * lo[:, 0]).astype(np.float64)
+    if d >= 2:
+        tot *= _range_count(n1, lo[:, 1], 0 * lo[:, 1], 0, lines)
+    if d == 3:
+        tot *= _range_count(n1, lo[:, 2], 0 * lo[:, 2], 0, 1)
+    return float(tot.sum())
+
+
+KERNEL_SOURCES = {"factor": ("paper_2004_13961_amd/csrc/ilu.hip", "paper_2004_13961_amd/csrc/ilu3d.hip"),
+                  "sweep": ("paper_2004_13961_amd/csrc/ilu.hip", "paper_2004_13961_amd/csrc/ilu3d.hip"),
+                  "matvec": ("paper_2004_13961_amd/csrc/gemm.hip",)}
 
 
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed counter figures
-    (profiles/traffic_<kernel>_<workload>.json: FETCH_SIZE and WRITE_SIZE per
-    dispatch, scaled by what the same counters read for a copy of known
-    size). None when there are none or the kernel's source file changed since
-    they were taken."""
-    import hashlib
+    (profiles/traffic_<kernel>_<workload>.json), or None when there are none
+    or the kernel's sources changed since they were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    with open(os.path.join(ROOT, KERNEL_SOURCES[kernel]), "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
-    if rec.get("source_sha256") != digest:
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("sources_sha256") != h.hexdigest():
         return None
     return rec.get("bytes_per_launch")
 
@@ -125,12 +234,12 @@ def measured_traffic(kernel, workload):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="2d_N1024_T8", help="2d_N32_T4, 2d_N1024_T8, 3d_N128_T6 or 3d_N256_T6_mixed")
+    ap.add_argument("--workload", default="3d_N256_T6_mixed",
+                    help="3d_N256_T6_mixed (default), 3d_N128_T6, 2d_N1024_T8 or 2d_N32_T4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=100000)
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-sample-lines", type=int, default=64)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="finish with one device-to-device copy of this many bytes (a reference "
                          "for hardware byte counters)")
@@ -149,140 +258,148 @@ def main():
 
     cfg = synth.WORKLOADS[args.workload]
     d, N, T = cfg.d, cfg.N, cfg.T
+    mixed = cfg.mixed
+    # the FP64 factor of the 3D mixed workload does not fit in HBM: FP32 only
+    store = ("f32only" if d == 3 else "f32") if mixed else "f64"
+    inner = "f32" if mixed else "f64"
+    inner_rtol = 1e-4 if mixed else 0.0
     lgpcg.lib()
     a, b, f, _ = family_nodal(d, N, cfg.J, cfg.seed)
     dev = lambda v: torch.from_numpy(np.ascontiguousarray(v).reshape(-1)).cuda()
     a_d, b_d, f_d = dev(a), dev(b), dev(f)
+    del a, b, f
     torch.cuda.synchronize()
 
-    def one_request():
-        P = Problem(d, N, a_d, b_d)
-        M = Factor(P, T)
-        F = P.load_vector(f_d)
-        x, info = pcg_solve(P, M, F, rtol=cfg.tol)
-        return P, M, F, x, info
+    state = {}
 
-    log("config %s: inputs resident" % cfg.name)
+    def one_request():
+        state.clear()   # the previous request's buffers go before the next is built
+        P = Problem(d, N, a_d, b_d)
+        M = Factor(P, T, store=store)
+        F = P.load_vector(f_d)
+        x, info = pcg_solve(P, M, F, rtol=cfg.tol, inner=inner, inner_rtol=inner_rtol)
+        state.update(P=P, M=M, F=F, x=x, info=info)
+        return info
+
+    log("config %s: inputs resident; factor store %s, solve %s" % (cfg.name, store, inner))
     for _ in range(args.warmup):
         one_request()
     torch.cuda.synchronize()
     log("warmup done")
     t0 = time.perf_counter()
-    infos = []
-    for _ in range(args.steps):
-        P, M, F, x, info = one_request()
-        infos.append(info)
+    infos, fac_ms_list = [], []
+    for k in range(args.steps):
+        infos.append(one_request())
+        fac_ms_list.append(float(state["M"].describe()["factor_kernel_ms"]))
+        log("step %d done" % k)
     torch.cuda.synchronize()
     t_e2e = (time.perf_counter() - t0) / args.steps
     log("timed steps: %.3f ms/step" % (t_e2e * 1e3))
     for inf in infos:
         assert inf["relres_true"] <= cfg.tol, inf
+    P, M, F, x = state["P"], state["M"], state["F"], state["x"]
+    desc = M.describe()
+    n = P.n
 
     # solve only (factors built)
-    ws = torch.empty(lgpcg.lib().lgp_solve_workspace_bytes(P.handle, 0), dtype=torch.uint8, device="cuda")
-    x = torch.zeros_like(F)
-    pcg_solve(P, M, F, x=x, rtol=cfg.tol, ws=ws)
-    torch.cuda.synchronize()
-    reps = max(3, args.steps)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        x.zero_()
-        _, info_s = pcg_solve(P, M, F, x=x, rtol=cfg.tol, ws=ws)
-    torch.cuda.synchronize()
-    t_solve = (time.perf_counter() - t0) / reps
-    log("solve only: %.3f ms" % (t_solve * 1e3))
+    solve = {}
+    for inn in (("f32", "bf16") if mixed else ("f64",)):
+        xs = torch.zeros_like(F)
+        rt = inner_rtol if inn == "f32" else 0.0
+        pcg_solve(P, M, F, x=xs, rtol=cfg.tol, inner=inn, inner_rtol=rt)
+        torch.cuda.synchronize()
+        reps = 2 if d == 3 else max(3, args.steps)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            xs.zero_()
+            _, info_s = pcg_solve(P, M, F, x=xs, rtol=cfg.tol, inner=inn, inner_rtol=rt)
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t0) / reps
+        err = float(torch.linalg.norm(xs - x) / torch.linalg.norm(x))
+        solve[inn] = dict(solves_per_sec=round(1.0 / ts, 4), ms=round(ts * 1e3, 3), iters=info_s["iters"],
+                          outer=info_s["outer"], relres_true=info_s["relres_true"],
+                          rel_diff_vs_step_solution=err)
+        log("solve only (%s): %.3f ms, %s" % (inn, ts * 1e3, info_s))
+        del xs
 
-    # matvec and sweep timing with events on the library's stream
-    u = torch.rand(P.n, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(u)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    for _ in range(3):
-        P.matvec(u, y)
-    nmv = 20
-    ev[0].record()
-    for _ in range(nmv):
-        P.matvec(u, y)
-    ev[1].record()
-    nsw = 10
-    for _ in range(2):
-        M.forward(u, y)
-    ev[2].record()
-    for _ in range(nsw):
-        M.forward(u, y)
-    ev[3].record()
-    for _ in range(2):
-        M.backward(u, y)
-    ev[4].record()
-    for _ in range(nsw):
-        M.backward(u, y)
-    ev[5].record()
+    # matvec in each precision, substitutions, with events on the library's stream
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    mv = {}
+    u64 = torch.rand(n, dtype=torch.float64, device="cuda")
+    y64 = torch.empty_like(u64)
+    mv["f64"] = timed(lambda: P.matvec(u64, y64), 10)
+    del y64
+    u32 = u64.float()
+    del u64
+    y32 = torch.empty_like(u32)
+    mv["f32"] = timed(lambda: P.matvec(u32, y32, prec="f32"), 10)
+    mv["bf16"] = timed(lambda: P.matvec(u32, y32, prec="bf16"), 10)
+    mv_tf = {k: matvec_flops(d, N) / (v * 1e-3) / 1e12 for k, v in mv.items()}
+    if desc["L"] is not None:
+        sd = "f64"
+        uu = torch.rand(n, dtype=torch.float64, device="cuda")
+        yy = torch.empty_like(uu)
+        sw_ms = timed(lambda: M.forward(uu, yy), 3)
+        swb_ms = timed(lambda: M.backward(uu, yy), 3)
+        s_L = 8
+    else:
+        sd = "f32"
+        sw_ms = timed(lambda: M.forward32(u32, y32), 3)
+        swb_ms = timed(lambda: M.backward32(u32, y32), 3)
+        s_L = 4
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    M_t = Factor(P, T)
-    torch.cuda.synchronize()
-    t_factor = time.perf_counter() - t0
-    mv_ms = ev[0].elapsed_time(ev[1]) / nmv
-    sw_ms = ev[2].elapsed_time(ev[3]) / nsw
-    swb_ms = ev[4].elapsed_time(ev[5]) / nsw
-    mv_tflops = matvec_flops(d, N) / (mv_ms * 1e-3) / 1e12
-    desc = M.describe()
-    fac_ms = float(M_t.describe()["factor_kernel_ms"])   # ILU(0) kernel, HIP events on the library's stream
-    nnz = nnz_lower(d, N - 1, desc["offsets"])
-    n = P.n
-    sweep_bytes = nnz * 8 + 2 * n * 8      # L entries in the grid, r read, y written
+    offsets = desc["offsets"]
+    nnz = lower_entries(d, N - 1, offsets)
+    sweep_bytes = nnz * s_L + 2 * n * s_L
     sw_gbs = sweep_bytes / (sw_ms * 1e-3) / 1e9
-    # ILU(0): every in-grid entry of L and every pivot written once, and each
-    # row of L read at least once by the rows that use it
-    factor_bytes = 2 * (nnz + n) * 8
+    fac_ms = float(np.median(fac_ms_list))
+    log("matvec %s ms; sweeps %.3f / %.3f ms (%s); factor kernel %.1f ms" % (
+        {k: round(v, 4) for k, v in mv.items()}, sw_ms, swb_ms, sd, fac_ms))
 
-    iters = info_s["iters"]
-    # time of each candidate kernel inside one step
-    share = {"factor": fac_ms, "sweep": iters * (sw_ms + swb_ms), "matvec": (iters + 2) * mv_ms}
+    # dominant kernel of the timed step, by time share
+    info = infos[-1]
+    it = info["iters"]
+    sweeps_per_step = 2 * it
+    share = {"factor": fac_ms, "sweep": sweeps_per_step * (sw_ms + swb_ms) / 2,
+             "matvec": (it + 2 * max(1, info["outer"])) * mv[inner if inner != "f64" else "f64"]}
     dominant = max(share, key=share.get)
     if dominant == "factor":
-        ach = factor_bytes / (fac_ms * 1e-3) / 1e9
-        fk = "ilu_factor2_kernel" if desc.get("factor_kernel") == 2 else "ilu_factor_kernel"
-        roof = dict(kernel=fk + " (ILU(0), Alg. 2)", bound="hbm", achieved=round(ach, 2),
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 6),
-                    bytes_per_launch=factor_bytes, launch_ms=round(fac_ms, 3))
+        flops = 2.0 * ilu_pairs(d, N - 1, offsets) + 3.0 * nnz + 2.0 * n
+        ach = flops / (fac_ms * 1e-3) / 1e12
+        fk = {3: "ilu3d_factor_kernel", 2: "ilu_factor2_kernel", 1: "ilu_factor_kernel"}.get(
+            desc["factor_kernel"], "ilu_factor_kernel")
+        roof = dict(kernel=fk + " (ILU(0), Alg. 2, FP64)", bound="alu", achieved=round(ach, 4),
+                    peak=FP64_VECTOR_TFLOPS, unit="TFLOP/s", frac=round(ach / FP64_VECTOR_TFLOPS, 6),
+                    flops_per_launch=flops, bytes_written=nnz * (4 if store == "f32only" else 8),
+                    launch_ms=round(fac_ms, 3))
     elif dominant == "sweep":
-        sk = "sweep2d_pair_kernel" if d == 2 else "sweep_kernel"
-        roof = dict(kernel=sk + " (forward substitution, Alg. 3)", bound="hbm",
+        sk = "sweep3d_kernel" if d == 3 else "sweep2d_pair_kernel"
+        roof = dict(kernel=sk + " (forward substitution, Alg. 3, %s)" % sd, bound="hbm",
                     achieved=round(sw_gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(sw_gbs / HBM_PEAK_GBS, 5), bytes_per_launch=sweep_bytes,
                     launch_ms=round(sw_ms, 4))
     else:
-        roof = dict(kernel="gemm_k4_kernel<double> (sum-factorised matvec)", bound="mfma",
-                    achieved=round(mv_tflops, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(mv_tflops / FP64_PEAK_TFLOPS, 5), flops_per_matvec=matvec_flops(d, N),
-                    launch_ms=round(mv_ms, 4))
+        pm = inner if inner != "f64" else "f64"
+        roof = dict(kernel="gemm_k4_kernel (sum-factorised matvec, %s)" % pm, bound="mfma",
+                    achieved=round(mv_tf[pm], 3), peak=PEAK_TFLOPS[pm], unit="TFLOP/s",
+                    frac=round(mv_tf[pm] / PEAK_TFLOPS[pm], 5), flops_per_launch=matvec_flops(d, N),
+                    launch_ms=round(mv[pm], 4))
     roof["traffic"] = measured_traffic(dominant, cfg.name)
     roof["time_share_ms"] = {k: round(v, 3) for k, v in share.items()}
 
-    log("matvec %.4f ms, sweeps %.4f / %.4f ms, factor %.1f ms (kernel %.1f ms)" % (mv_ms, sw_ms, swb_ms,
-                                                                                   t_factor * 1e3, fac_ms))
-    mixed = {}
-    if not args.no_mixed:
-        xd = x.clone()
-        M32 = Factor(P, T, store="f32")
-        for inner in ("f32", "bf16"):
-            xm = torch.zeros_like(F)
-            pcg_solve(P, M32, F, x=xm, rtol=cfg.tol, inner=inner)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(2):
-                xm.zero_()
-                _, im = pcg_solve(P, M32, F, x=xm, rtol=cfg.tol, inner=inner)
-            torch.cuda.synchronize()
-            tm = (time.perf_counter() - t0) / 2
-            log("mixed %s: %.3f ms, %s" % (inner, tm * 1e3, im))
-            err = float(torch.linalg.norm(xm - xd) / torch.linalg.norm(xd))
-            mixed[inner] = dict(solves_per_sec=round(1.0 / tm, 3), inner_iters=im["iters"], outer=im["outer"],
-                                relres_true=im["relres_true"], rel_err_vs_fp64=err)
-
     out = {
         "metric": "PCG solves/sec + matvec TFLOP/s at rel. residual 1e-10, mixed vs FP64",
-        "value": round(1.0 / t_e2e, 4),
+        "value": round(1.0 / t_e2e, 5),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -291,36 +408,35 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if not mixed else "f64+f32",
         "data": "synthetic",
         "config": {"workload": cfg.name, "d": d, "N": N, "T": T, "unknowns": n, "tol": cfg.tol,
-                   "coefficients": "a = 2 + sum_{j,k<=%d} c_jk L_j L_k, seed %d; b = 1+|x|^2" % (cfg.J, cfg.seed),
-                   "step": "build operator + factor M (ILU(0), FP64) + load vector + PCG to 1e-10"},
-        "solve_only_per_sec": round(1.0 / t_solve, 3),
-        "solve_only_ms": round(t_solve * 1e3, 3),
-        "pcg_iterations": iters,
-        "relres_true": info_s["relres_true"],
-        "factor_ms": round(t_factor * 1e3, 3),
-        "matvec_ms": round(mv_ms, 4),
-        "matvec_tflops": round(mv_tflops, 3),
-        "matvec_frac_fp64_peak": round(mv_tflops / FP64_PEAK_TFLOPS, 4),
+                   "coefficients": "a = 2 + sum_{j<=%d} c_j L_j..., seed %d; b = 1+|x|^2" % (cfg.J, cfg.seed),
+                   "factor_store": store, "solve": inner if not mixed else "FP64 refinement, FP32 inner (1e-4)",
+                   "step": "build operator + factor M (ILU(0) in FP64) + load vector + solve to 1e-10"},
+        "pcg_iterations": it,
+        "outer": info["outer"],
+        "relres_true": info["relres_true"],
+        "factor_kernel_ms": round(fac_ms, 3),
+        "solve_only": solve,
+        "matvec_ms": {k: round(v, 4) for k, v in mv.items()},
+        "matvec_tflops": {k: round(v, 3) for k, v in mv_tf.items()},
+        "matvec_frac_peak": {k: round(mv_tf[k] / PEAK_TFLOPS[k], 5) for k in mv_tf},
         "sweep_ms": round(sw_ms, 4),
         "sweep_backward_ms": round(swb_ms, 4),
-        "factor_kernel_ms": round(fac_ms, 3),
+        "sweep_dtype": sd,
         "sweep_gbs": round(sw_gbs, 2),
-        "sweep_levels": desc["levels"],
-        "mixed": mixed,
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": roof,
     }
+    del state, P, M, F, x, u32, y32
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("oracle on the host CPU (bounded sample)")
-        cb = cpu_baseline(cfg, args.cpu_sample_rows)
-        total = cb["setup"] + cb["t_iter"] * iters
-        out["cpu_baseline"] = {"value": round(1.0 / total, 6), "unit": "solves/s", "cores": cb["threads"],
-                               "kind": "oracle",
-                               "sample": cb["sample"] + "; total scaled to the GPU's %d iterations" % iters}
-    print(json.dumps(out))
+        cb = cpu_baseline(cfg, args.cpu_sample_lines, max(1, it))
+        out["cpu_baseline"] = {"value": float("%.4g" % (1.0 / cb["total"])), "unit": "solves/s",
+                               "cores": cb["threads"], "kind": "oracle", "sample": cb["sample"]}
+    print(json.dumps(out), flush=True)
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

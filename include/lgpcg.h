@@ -56,7 +56,9 @@ typedef enum {
     LGP_E_UNSUPPORTED = 8 /* valid request the library does not serve */
 } lgp_status;
 
-typedef enum { LGP_F64 = 0, LGP_F32 = 1, LGP_BF16 = 2 } lgp_dtype;
+/* Precisions. LGP_F32_ONLY is a factor storage only (lgp_factor_M, d = 3):
+ * the factor is kept in FP32 alone, for mixed-precision solves. */
+typedef enum { LGP_F64 = 0, LGP_F32 = 1, LGP_BF16 = 2, LGP_F32_ONLY = 3 } lgp_dtype;
 
 typedef struct lgp_problem_s* lgp_problem;
 typedef struct lgp_factor_s* lgp_factor;
@@ -116,7 +118,12 @@ lgp_status lgp_matvec(lgp_problem p, const void* u, void* y, lgp_dtype prec, voi
 /* ------------------------------------------------------ preconditioner -- */
 /* Device bytes for the ILU(0) factors of M with truncation degrees Ta (for
  * a) and Tb (for b); store = LGP_F32 adds single-precision copies of the
- * factors for the inner sweeps of the mixed-precision solve. */
+ * factors for the inner sweeps of the mixed-precision solve; store =
+ * LGP_F32_ONLY (d = 3) keeps the single-precision factor alone (the
+ * factorisation still runs in FP64, over a window of the rows still being
+ * read, at most 24 GiB): such a factor serves mixed-precision solves only,
+ * and an FP64 solve with it returns LGP_E_UNSUPPORTED. Returns 0 for a
+ * store the dimension does not take. */
 size_t lgp_factor_bytes(lgp_problem p, int Ta, int Tb, lgp_dtype store);
 
 /* Preconditioner of Sec. 4.1: a and b replaced by their Legendre series
@@ -176,6 +183,12 @@ lgp_status lgp_precond_apply(lgp_factor m, const double* r, double* z, void* str
 /* The two halves separately: y = L^{-1} r (Alg. 3) and z = U^{-1} y (Alg. 4). */
 lgp_status lgp_ilu_forward(lgp_factor m, const double* r, double* y, void* stream);
 lgp_status lgp_ilu_backward(lgp_factor m, const double* y, double* z, void* stream);
+/* The same two substitutions in single precision on the FP32 copy of the
+ * factor (the inner sweeps of the mixed-precision solve): r, y, z device
+ * (N-1)^d floats, must not alias. LGP_E_UNSUPPORTED for a factor without an
+ * FP32 copy (store = LGP_F64) or from lgp_factor_const. */
+lgp_status lgp_ilu_forward_f32(lgp_factor m, const float* r, float* y, void* stream);
+lgp_status lgp_ilu_backward_f32(lgp_factor m, const float* y, float* z, void* stream);
 
 /* Layout of a factor, for inspection. offsets (host, 3*noff ints, filled by
  * the library and valid while the handle lives) lists NZ(M) as (dx,dy,dz) in
@@ -197,10 +210,16 @@ typedef struct {
                                 from HIP events on the caller's stream (-1 if unknown) */
     int factor_kernel;   /* which ILU(0) kernel built it: 2 = dataflow kernel (one row per
                             wavefront, pair tables in LDS), 1 = generic level-ordered kernel
-                            (for d = 1: the single-wavefront band factorisation).
+                            (for d = 1: the single-wavefront band factorisation),
+                            3 = chunked kernel of d = 3 (a workgroup per run of rows of
+                            a grid line, FP64 rows in a window).
                             The environment variable LGP_FACTOR_KERNEL=1|2 restricts the
-                            choice to that kernel where it applies (else the generic one
+                            2D choice to that kernel where it applies (else the generic one
                             runs); unset or 0 takes 2 where it applies. */
+    int layout;          /* 0: L row-major as above. 1 (d = 3): offset-major,
+                            L[k*ld + i] = L(i, i + offset_k) with ld >= n; L is NULL
+                            when the factor is kept in FP32 only */
+    const double* invD;  /* device, n: 1/U(i,i) */
 } lgp_factor_desc;
 lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out);
 

@@ -122,14 +122,16 @@ int64_t ilu0_stencil(int d, int n1, int noff, const int *off, double *H, int64_t
     return 0;
 }
 
-/* Alg. 3: L y = r with L unit lower (strict part in H). */
-void forward_stencil(int d, int n1, int noff, const int *off, const double *H,
-                     const double *r, double *y) {
+/* Alg. 3: L y = r with L unit lower (strict part in H), for rows
+   0..nrows-1 (nrows < 0: all rows; a prefix only reads earlier rows). */
+void forward_stencil_rows(int d, int n1, int noff, const int *off, const double *H,
+                          const double *r, double *y, int64_t nrows) {
     grid_t g = {d, n1, noff, -1, off};
     for (int o = 0; o < noff; ++o)
         if (off[3 * o] == 0 && off[3 * o + 1] == 0 && off[3 * o + 2] == 0) g.diag = o;
     int64_t n = 1;
     for (int k = 0; k < d; ++k) n *= n1;
+    if (nrows >= 0 && nrows < n) n = nrows;
     for (int64_t i = 0; i < n; ++i) {
         int c[3];
         coords(&g, i, c);
@@ -141,6 +143,11 @@ void forward_stencil(int d, int n1, int noff, const int *off, const double *H,
         }
         y[i] = r[i] - acc;
     }
+}
+
+void forward_stencil(int d, int n1, int noff, const int *off, const double *H,
+                     const double *r, double *y) {
+    forward_stencil_rows(d, n1, noff, off, H, r, y, -1);
 }
 
 /* Alg. 4: U z = y with U upper (diagonal and upper part in H). */

@@ -91,6 +91,9 @@ def _clib():
         for f in (_lib.forward_stencil, _lib.backward_stencil):
             f.restype = None
             f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp]
+        _lib.forward_stencil_rows.restype = None
+        _lib.forward_stencil_rows.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, dp,
+                                              ctypes.c_int64]
     return _lib
 
 
@@ -134,6 +137,16 @@ class StencilILU:
         _clib().forward_stencil(self.d, self.n1, len(self.offsets),
                                 _p(self.off, ctypes.c_int), _p(self.H, ctypes.c_double),
                                 _p(r, ctypes.c_double), _p(y, ctypes.c_double))
+        return y
+
+    def forward_prefix(self, r, nrows: int):
+        """Alg. 3 over the first `nrows` rows only (rows read earlier rows
+        only; used to time a bounded sample on a prefix of the rows)."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        y = np.zeros_like(r)
+        _clib().forward_stencil_rows(self.d, self.n1, len(self.offsets),
+                                     _p(self.off, ctypes.c_int), _p(self.H, ctypes.c_double),
+                                     _p(r, ctypes.c_double), _p(y, ctypes.c_double), nrows)
         return y
 
     def backward(self, y):

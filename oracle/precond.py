@@ -349,16 +349,19 @@ def _diag_of(F: np.ndarray, delta: int) -> np.ndarray:
 
 
 def stencil_rows(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray, offsets,
-                 S=None, Mm=None) -> np.ndarray:
+                 S=None, Mm=None, nplanes: int = None) -> np.ndarray:
     """H[row, o] = M(row, row + offsets[o]) for every row, from the Kronecker
     form (each term separable, so each offset is a tensor product of 1D
-    diagonals contracted with the coefficient array). d = 1, 2, 3."""
+    diagonals contracted with the coefficient array). d = 1, 2, 3. For d = 3,
+    `nplanes` keeps the rows of the first nplanes z-planes only (a prefix of
+    the rows, for timing a bounded sample)."""
     a_dir = _a_list(ahat, d)
     Tb = bhat.shape[0] - 1
     T = max(max(ah.shape[0] - 1 for ah in a_dir), Tb)
     if S is None:
         S, Mm = band_factors(n1, T)
-    n = n1 ** d
+    nz = n1 if (d != 3 or nplanes is None) else min(nplanes, n1)
+    n = n1 ** (d - 1) * nz if d == 3 else n1 ** d
     H = np.zeros((n, len(offsets)))
     Ad = []                                # per direction, padded to T
     for ah in a_dir:
@@ -370,6 +373,8 @@ def stencil_rows(d: int, n1: int, ahat: np.ndarray, bhat: np.ndarray, offsets,
     for o, off in enumerate(offsets):
         Sd = [np.stack([_diag_of(S[t], off[k]) for t in range(T + 1)]) for k in range(d)]
         Md = [np.stack([_diag_of(Mm[t], off[k]) for t in range(T + 1)]) for k in range(d)]
+        if d == 3:
+            Sd[2], Md[2] = Sd[2][:, :nz], Md[2][:, :nz]
         def term(C, Fz, Fy, Fx):
             # sum_{r,s,t} C[r,s,t] Fz[r,z] Fy[s,y] Fx[t,x], one direction at a time
             if d == 2:

@@ -256,6 +256,11 @@ static void init_factor_dims(Factor& F, const Problem& P, const int* Tdir, int T
     F.levels = 0;
 }
 
+// factor storage: FP64; FP64 and FP32; FP32 only (d = 3)
+static bool valid_store(const Problem& P, lgp_dtype store) {
+    return store == LGP_F64 || store == LGP_F32 || (store == LGP_F32_ONLY && P.d == 3);
+}
+
 static bool valid_truncations(const Problem& P, const int* Tdir, int Tb) {
     if (!Tdir || Tb < 0 || Tb > 24) return false;
     for (int j = 0; j < P.d; ++j)
@@ -264,7 +269,7 @@ static bool valid_truncations(const Problem& P, const int* Tdir, int Tb) {
 }
 
 size_t lgp_factor_bytes_dir(lgp_problem p, const int* Ta_dir, int Tb, lgp_dtype store) {
-    if (!p || !valid_truncations(p->P, Ta_dir, Tb)) return 0;
+    if (!p || !valid_truncations(p->P, Ta_dir, Tb) || !valid_store(p->P, store)) return 0;
     Factor F;
     init_factor_dims(F, p->P, Ta_dir, Tb);
     // upper bound: the full box |delta_k| <= h
@@ -273,7 +278,7 @@ size_t lgp_factor_bytes_dir(lgp_problem p, const int* Ta_dir, int Tb, lgp_dtype 
     for (int k = 0; k < p->P.d; ++k) tp *= (size_t)T1;
     std::vector<double> ones(tp, 1.0), ones_a((size_t)p->P.d * tp, 1.0);
     set_pattern(F, pattern_offsets(p->P.d, F.T, ones_a, ones));
-    return plan_factor(F, nullptr, store != LGP_F64);
+    return plan_factor(F, nullptr, (int)store);
 }
 
 size_t lgp_factor_bytes(lgp_problem p, int Ta, int Tb, lgp_dtype store) {
@@ -285,7 +290,7 @@ lgp_status lgp_factor_M_dir(lgp_problem p, const int* Ta_dir, int Tb, lgp_dtype 
                             void* stream, lgp_factor* out) {
     if (!out) return LGP_E_ARG;
     *out = nullptr;
-    if (!p || !buf || !valid_truncations(p->P, Ta_dir, Tb)) return LGP_E_ARG;
+    if (!p || !buf || !valid_truncations(p->P, Ta_dir, Tb) || !valid_store(p->P, store)) return LGP_E_ARG;
     if (buf_bytes < lgp_factor_bytes_dir(p, Ta_dir, Tb, store)) return LGP_E_NOMEM;
     LGP_ONE_THREAD();
     Problem& P = p->P;
@@ -394,7 +399,7 @@ lgp_status lgp_factor_M_dir(lgp_problem p, const int* Ta_dir, int Tb, lgp_dtype 
     for (size_t ci = 0; ci < tp; ++ci)
         if (std::fabs(cb[ci]) <= 1e-13 * mx) cb[ci] = 0.0;
     set_pattern(F, pattern_offsets(d, T, ca, cb));
-    if (plan_factor(F, buf, store != LGP_F64) > buf_bytes) {
+    if (plan_factor(F, buf, (int)store) > buf_bytes) {
         factor_release(hF->F);
         delete hF;
         return LGP_E_NOMEM;
@@ -479,6 +484,20 @@ lgp_status lgp_ilu_backward(lgp_factor m, const double* y, double* z, void* stre
     return sweep(m->F, true, y, z, (hipStream_t)stream);
 }
 
+lgp_status lgp_ilu_forward_f32(lgp_factor m, const float* r, float* y, void* stream) {
+    if (!m || !r || !y || (const void*)r == (const void*)y) return LGP_E_ARG;
+    if (m->F.kind != 0 || !m->F.has32) return LGP_E_UNSUPPORTED;
+    LGP_ONE_THREAD();
+    return sweep32(m->F, false, r, y, (hipStream_t)stream);
+}
+
+lgp_status lgp_ilu_backward_f32(lgp_factor m, const float* y, float* z, void* stream) {
+    if (!m || !y || !z || (const void*)y == (const void*)z) return LGP_E_ARG;
+    if (m->F.kind != 0 || !m->F.has32) return LGP_E_UNSUPPORTED;
+    LGP_ONE_THREAD();
+    return sweep32(m->F, true, y, z, (hipStream_t)stream);
+}
+
 lgp_status lgp_precond_apply(lgp_factor m, const double* r, double* z, void* stream) {
     if (!m || !r || !z || r == z) return LGP_E_ARG;
     LGP_ONE_THREAD();
@@ -501,12 +520,14 @@ lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out) {
     out->noff = F.noff;
     out->n_lower = F.nlo;
     out->offsets = F.offs.data();
-    out->L = F.L;
+    out->L = F.layout == 1 ? F.A64 : F.L;
     out->D = F.Dg;
     out->levels = F.levels;
-    out->ld = F.ldl;
+    out->ld = F.layout == 1 ? (int)F.ldo : F.ldl;
     out->factor_kernel_ms = F.factor_kernel_ms;
     out->factor_kernel = F.factor_kernel;
+    out->layout = F.layout;
+    out->invD = F.invD;
     return LGP_OK;
 }
 

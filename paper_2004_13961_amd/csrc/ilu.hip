@@ -28,7 +28,7 @@
 #include <map>
 #include <mutex>
 
-#include "lgp_internal.h"
+#include "devutil.h"
 
 namespace lgp {
 
@@ -71,7 +71,11 @@ __host__ __device__ static inline double M1(int t, int i, int m) {
            triple_legendre(t, i + 2, m + 2);
 }
 
-size_t plan_factor(Factor& F, void* buf, bool with32) {
+size_t plan_factor(Factor& F, void* buf, int store) {
+    if (F.d == 3) return plan_factor3(F, buf, store);
+    const bool with32 = (store != STORE_F64);
+    F.has64 = true;
+    F.layout = 0;
     Carver c(buf);
     const int64_t n = F.n;
     const int nlo = F.nlo;
@@ -121,72 +125,6 @@ size_t plan_factor(Factor& F, void* buf, bool with32) {
     F.y_tmp = c.take<double>(n);
     F.bytes = c.off + 256;
     return F.bytes;
-}
-
-// ------------------------------------------------------ device helpers ---
-// Values produced and consumed inside one kernel by different workgroups
-// (substitution results, factor rows, pivots, progress flags) travel through
-// device-coherent accesses: relaxed device-scope atomic loads and stores,
-// which the compiler emits as sc1 global accesses and which need no L2
-// write-back or invalidate. A producer waits for its own stores to complete
-// (s_waitcnt vmcnt(0)) before it publishes a flag, so a consumer that has
-// seen the flag and then loads coherently sees the data. Data written by an
-// earlier kernel (the factors, the right-hand side) is read with ordinary
-// cached loads.
-template <typename T>
-__device__ inline T ld_coh(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ inline void st_coh(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void wait_own_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-__device__ inline void compiler_fence() { asm volatile("" ::: "memory"); }
-__device__ inline void publish(unsigned* flag, unsigned v) {
-    wait_own_stores();
-    st_coh(flag, v);
-}
-
-__device__ inline double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ inline float wave_sum(float v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Wave-wide sum with DPP lane moves inside each row of 16 lanes (pair swap,
-// quad swap, half-row mirror, row mirror), then the four row sums combined
-// through readlane; every lane returns the same value.
-template <int CTRL>
-__device__ inline int dpp_i(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ inline double dpp_v(double v) {
-    const int lo = dpp_i<CTRL>(__double2loint(v));
-    const int hi = dpp_i<CTRL>(__double2hiint(v));
-    return __hiloint2double(hi, lo);
-}
-template <int CTRL>
-__device__ inline float dpp_v(float v) {
-    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
-}
-__device__ inline double lane_val(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-__device__ inline float lane_val(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
-template <typename T>
-__device__ inline T wave_sum_dpp(T v) {
-    v += dpp_v<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_v<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp_v<0x141>(v);   // row_half_mirror
-    v += dpp_v<0x140>(v);   // row_mirror
-    return (lane_val(v, 0) + lane_val(v, 16)) + (lane_val(v, 32) + lane_val(v, 48));
 }
 
 struct RowGeo {
@@ -528,29 +466,6 @@ __global__ __launch_bounds__(NT) void sweep_kernel(int d, int n1, int64_t n, int
     }
 }
 
-// Sentinel marking a substitution result that is not written yet: a NaN
-// payload that arithmetic never produces (computed NaNs are stored as the
-// canonical quiet NaN instead), so polling the value itself tells a
-// consumer whether it is ready.
-template <typename T> struct Sentinel;
-template <> struct Sentinel<double> {
-    static __device__ __host__ inline double value() { return __longlong_as_double(0x7FF40000DEADBEEFll); }
-    static __device__ inline bool is(double v) { return __double_as_longlong(v) == 0x7FF40000DEADBEEFll; }
-    static __device__ inline double clean(double v) { return isnan(v) ? __longlong_as_double(0x7FF8000000000000ll) : v; }
-};
-template <> struct Sentinel<float> {
-    static __device__ __host__ inline float value() { return __int_as_float(0x7FA0BEEF); }
-    static __device__ inline bool is(float v) { return __float_as_int(v) == 0x7FA0BEEF; }
-    static __device__ inline float clean(float v) { return isnan(v) ? __int_as_float(0x7FC00000) : v; }
-};
-
-template <typename T>
-__global__ void fill_sentinel_kernel(int64_t n, T* __restrict__ out, const int* __restrict__ stop) {
-    if (stop && *stop) return;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = Sentinel<T>::value();
-}
-
 // 2D substitution, banded. A workgroup owns B consecutive grid lines (one
 // wave per line) and walks them as a pipeline; all operands of the row dot
 // products come from LDS, which holds full lines: the Hy lines preceding
@@ -810,28 +725,6 @@ __device__ inline double dpp_bcast15(double v) {
 __device__ inline float dpp_bcast15(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
 }
-// Wave total with DPP only: sums inside rows of 16 lanes, row_bcast15 adds
-// row 0 into row 1 and row 2 into row 3, row_bcast31 adds lane 31 into rows
-// 2 and 3; lane 63 then holds the total, read once into scalar registers.
-// The moves carry no old value (no register copies); lanes of the rows a
-// broadcast leaves out hold junk afterwards, but no later stage reads them
-// on the way to lane 63.
-template <int CTRL, int ROWS>
-__device__ inline double dpp_mov(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROWS, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROWS, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ inline double wave_total_bcast(double v) {
-    v += dpp_mov<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141, 0xF>(v);   // row_half_mirror
-    v += dpp_mov<0x140, 0xF>(v);   // row_mirror
-    v += dpp_mov<0x142, 0xA>(v);   // row_bcast15 into rows 1, 3
-    v += dpp_mov<0x143, 0xC>(v);   // row_bcast31 into rows 2, 3
-    return lane_val(v, 63);
-}
-
 template <typename T, int SL, int D, int NW, bool REV, bool SCALE, bool STAGE>
 __device__ inline void pair_walk(int n1, int64_t n, int ldl, int first, int lbase, int Hx, int Hy, int Wd,
                                  int zslot, const int (&boff)[SL], const int (&bstep)[SL],
@@ -1552,6 +1445,72 @@ lgp_status factor_build(Factor& F, hipStream_t s) {
     return st;
 }
 
+lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hipEvent_t* ev);
+lgp_status factor3_generic_finish(Factor& F, hipStream_t s);
+
+// d = 3: folded coefficients, then the chunked kernel (offset-major output
+// through the FP64 window) or, for stencils whose rows do not fit LDS, the
+// generic kernel on row-major rows followed by the conversion.
+static lgp_status factor_build3_impl(Factor& F, hipStream_t s, FactorHostTables& H, hipEvent_t* ev) {
+    const int d = 3, n1 = F.n1, T = F.T, h = F.h;
+    const int64_t n = F.n;
+    // pair words: the packets of the chunked kernel read up to 64 * 8 words past a list
+    LGP_HIP(hipMemsetAsync(F.pairw + F.npairs, 0, 64 * 8 * 4, s));
+    hipLaunchKernelGGL(fold_kernel, dim3(std::min(F.nlines, 4096)), dim3(256), 0, s, d, n1, T, h,
+                       (const double*)F.band, (const double*)F.coefA, (const double*)F.coefB, F.fold3, F.nlines);
+    LGP_CHECK_LAUNCH();
+    if (F.fB > 0) return factor3_run(F, s, H.st4, ev);
+    // generic kernel: rows in level order, done flags in y_tmp, rows of L in
+    // the window (which holds the whole grid here)
+    F.factor_kernel = 1;
+    const int64_t A1 = F.Hx + 1, B1 = (int64_t)(F.Hx + 1) * (F.Hy + 1);
+    const int64_t maxlev = (n1 - 1) * (1 + A1 + B1) + 1;
+    if (maxlev > F.maxlev) return LGP_E_ARG;
+    F.levels = (int)maxlev;
+    std::vector<int>& lstart = H.lstart;
+    lstart.assign(2 * maxlev + 2, 0);
+    {
+        std::vector<int> diff(maxlev + 1, 0);
+        for (int iz = 0; iz < n1; ++iz)
+            for (int iy = 0; iy < n1; ++iy) {
+                const int64_t b0 = A1 * iy + B1 * iz;
+                diff[b0] += 1;
+                diff[b0 + n1] -= 1;
+            }
+        int run = 0, acc = 0;
+        for (int64_t l = 0; l < maxlev; ++l) {
+            run += diff[l];
+            lstart[l] = acc;
+            acc += run;
+        }
+        lstart[maxlev] = acc;
+        if (acc != n) return LGP_E_ARG;
+    }
+    LGP_HIP(hipMemcpyAsync(F.lev, lstart.data(), lstart.size() * 4, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(F.pair_ptr, H.ptr.data(), H.ptr.size() * 4, hipMemcpyHostToDevice, s));
+    if (F.npairs > 0) {
+        LGP_HIP(hipMemcpyAsync(F.pair_j, H.pk.data(), H.pk.size() * 4, hipMemcpyHostToDevice, s));
+        LGP_HIP(hipMemcpyAsync(F.pair_l, H.pl.data(), H.pl.size() * 4, hipMemcpyHostToDevice, s));
+    }
+    int* d_order = F.line_order;
+    hipLaunchKernelGGL(level_order_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256), 0, s,
+                       d, n1, n, (int)A1, (int)B1, (const int*)F.lev, F.lev + maxlev + 1, d_order);
+    LGP_HIP(hipMemsetAsync(F.ticket, 0, 16, s));
+    LGP_HIP(hipMemsetAsync(F.flag, 0, 16, s));
+    unsigned* done = (unsigned*)F.y_tmp;
+    LGP_HIP(hipMemsetAsync(done, 0, (size_t)n * 4, s));
+    const size_t shmem = (size_t)(F.nlo + 1) * 8;
+    const int grid = persistent_grid((const void*)ilu_factor_kernel, 64, shmem, n);
+    if (ev) hipEventRecord(ev[0], s);
+    hipLaunchKernelGGL(ilu_factor_kernel, dim3(grid), dim3(64), shmem, s, d, n1, n, F.nlo, F.ldl, T, h,
+                       (const int4*)F.d_offs, (const int*)d_order, (const double*)F.band, (const double*)F.fold3,
+                       (const int*)F.pair_ptr, (const int*)F.pair_j, (const int*)F.pair_l, F.ring, F.Dg, F.invD,
+                       done, F.ticket, F.flag);
+    LGP_CHECK_LAUNCH();
+    if (ev) hipEventRecord(ev[1], s);
+    return factor3_generic_finish(F, s);
+}
+
 static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& H, hipEvent_t* ev) {
     if (F.d == 1) {
         if (ev) hipEventRecord(ev[0], s);
@@ -1661,6 +1620,7 @@ static lgp_status factor_build_impl(Factor& F, hipStream_t s, FactorHostTables& 
         LGP_HIP(hipMemcpyAsync(F.sdxyz, sd.data(), sd.size() * 4, hipMemcpyHostToDevice, s));
         if (!pw.empty()) LGP_HIP(hipMemcpyAsync(F.pairw, pw.data(), pw.size() * 4, hipMemcpyHostToDevice, s));
     }
+    if (d == 3) return factor_build3_impl(F, s, H, ev);
     LGP_HIP(hipMemcpyAsync(F.pair_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, s));
     if (F.npairs > 0) {
         LGP_HIP(hipMemcpyAsync(F.pair_j, pk.data(), pk.size() * 4, hipMemcpyHostToDevice, s));
@@ -1885,6 +1845,7 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
 }
 
 lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStream_t s, const int* stop) {
+    if (F.layout == 1) return sweep3(F, backward, false, in, out, s, stop);
     if (F.d == 1) return band1d_sweep<double>(F, backward, F.L, F.invD, in, out, s, stop);
     return backward ? sweep_t<double>(F, true, F.Ut, F.invD, in, out, s, stop)
                     : sweep_t<double>(F, false, F.L, nullptr, in, out, s, stop);
@@ -1892,6 +1853,7 @@ lgp_status sweep(Factor& F, bool backward, const double* in, double* out, hipStr
 
 lgp_status sweep32(Factor& F, bool backward, const float* in, float* out, hipStream_t s, const int* stop) {
     if (!F.has32) return LGP_E_ARG;
+    if (F.layout == 1) return sweep3(F, backward, true, in, out, s, stop);
     if (F.d == 1) return band1d_sweep<float>(F, backward, F.L32, F.invD32, in, out, s, stop);
     return backward ? sweep_t<float>(F, true, F.Ut32, F.invD32, in, out, s, stop)
                     : sweep_t<float>(F, false, F.L32, nullptr, in, out, s, stop);

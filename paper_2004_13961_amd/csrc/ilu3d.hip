@@ -1,0 +1,776 @@
+// Three-dimensional preconditioner path: ILU(0) of M (Alg. 2) with the
+// factor written offset-major, and the two substitutions of the one-step
+// method (Alg. 3, Alg. 4) reading that layout.
+//
+// Storage. A[k * ldo + i] = L(i, i + delta_k) for the lower offsets delta_k
+// (zero where the column leaves the grid). For a run of consecutive rows i
+// the forward substitution reads A[k][i..] and the backward one, which needs
+// L(i - delta_k, i) = A[k][i - delta_k], reads A[k][i - delta_k ..]: both
+// are contiguous, so no transposed copy of the factor is kept. The FP64
+// factor may be omitted (FP32 copy only, for the mixed-precision solve):
+// the factorisation itself always runs in FP64 on a window of rows, the
+// `ring`, which holds each row from its completion until the last row that
+// reads it is done.
+//
+// Factorisation schedule. A chunk is B consecutive rows of one grid line
+// (fixed iy, iz); one workgroup of B waves takes a chunk, one wave per row.
+// With e = ceil(Hx / B), chunk keys kappa = xb + wy iy + wz iz,
+// wy = e + 1, wz = e + wy Hy + 1, decrease along every dependency between
+// different chunks (a row i + delta lies at most e chunks away in x), so
+// handing out chunks in key order by an atomic ticket means a row only
+// waits for rows of chunks taken earlier (resident or finished) or for the
+// earlier rows of its own chunk. Consecutive rows of a chunk read largely
+// the same rows of L at nearly the same time, from the same L2.
+//
+// Ring. The ring slot of a row is (rank of its chunk * B + ix mod B) mod R.
+// A launch covers chunks of keys [k0, k1) and reads rows of keys down to
+// k0 - reach (reach = e + wy Hy + wz Hz): the launches are cut so that all of
+// those rows fit in R slots, so no slot in use is overwritten; the slots a
+// launch writes are filled with the sentinel before it.
+//
+// Each row is computed left-looking (reading R1): u_j = M(i, i+d_j) -
+// sum over pairs (k, l) with d_k = d_j + d_l of u_k L(i+d_j, i+d_k), the
+// offsets j taken in the host's dataflow order; then L(i, i+d_j) = u_j /
+// D(i+d_j), D(i) = M(i,i) - sum_j u_j L(i, i+d_j). The pairs of all steps
+// form one list cut into packets of at most 64 (one per lane); the loads of
+// the next PP packets are in flight while a packet is consumed. A row's
+// entries are published together when it is done; a gathered sentinel sends
+// the step to coherent re-reads.
+//
+// Substitution schedule. Blocks of BX consecutive rows of a line; a
+// workgroup (256 threads: BX rows x 256/BX offset groups) sums the terms of
+// every other line for its rows in parallel, then one thread solves the
+// short in-line recurrence (offsets (-m, 0, 0)). Blocks are handed out in
+// the key order above (B = BX); a block waits until its own line has done
+// the previous block, and the lines (iy-1, iz) and (min(iy+Hy, n1-1), iz-1)
+// have done the columns it needs (by induction that covers every other
+// line). The backward substitution runs the same kernel on the mirrored
+// grid (stream row i' = n-1-i).
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
+#include "devutil.h"
+
+namespace lgp {
+
+// ------------------------------------------------------------ helpers ----
+struct ChunkKeys {
+    int e, wy, wz, reach;
+};
+static ChunkKeys chunk_keys(int B, int Hx, int Hy, int Hz) {
+    ChunkKeys k;
+    k.e = (Hx + B - 1) / B;
+    if (k.e < 1) k.e = 1;
+    k.wy = k.e + 1;
+    k.wz = k.e + k.wy * Hy + 1;
+    k.reach = k.e + k.wy * Hy + k.wz * Hz;
+    return k;
+}
+
+// waves per workgroup of the 3D factor kernel: each wave holds its row's
+// u vector (n_lower + 2 doubles) in LDS
+// pairs per lane in one packet of the 3D factor kernel
+constexpr int kPairsPerLane = 8;
+
+static int factor3_waves(int nlo) {
+    const size_t per = (size_t)(nlo + 2) * 8;
+    const int fit = (int)((150u * 1024u) / per);
+    int B = 8;   // a power of two (slot arithmetic by shifts)
+    while (B > fit) B >>= 1;
+    if (nlo + 2 > 8191) B = 0;   // pair words carry byte offsets in 16 bits
+    return B;
+}
+
+static int64_t ring_rows_for(const Factor& F, int64_t ldl) {
+    // at most 24 GiB of FP64 rows, never more than one slot per row of every
+    // chunk (nchunks * B >= n); LGP_RING_ROWS lowers it (tests of the
+    // windowed path on small grids)
+    int64_t R = (int64_t)((24ull << 30) / ((uint64_t)ldl * 8ull)) - 1;
+    const int64_t all = (int64_t)F.nchunks * F.fB;
+    if (R > all) R = all;
+    if (const char* e = std::getenv("LGP_RING_ROWS")) {
+        const long long v = std::atoll(e);
+        if (v > 0 && v < R) R = v;
+    }
+    // a whole number of chunks, so a chunk's slots never wrap
+    if (F.fB > 0) R = (R / F.fB) * F.fB;
+    return R;
+}
+
+size_t plan_factor3(Factor& F, void* buf, int store) {
+    Carver c(buf);
+    const int64_t n = F.n;
+    const int nlo = F.nlo, T = F.T, h = F.h, n1 = F.n1;
+    const int T1 = T + 1, W = 2 * h + 1;
+    const int64_t tp = (int64_t)T1 * T1 * T1;
+    F.layout = 1;
+    F.ldl = ((nlo + 1) + 31) & ~31;
+    F.ldo = (n + 63) & ~(int64_t)63;
+    F.has64 = (store != STORE_F32_ONLY);
+    F.has32 = (store != STORE_F64);
+    F.fB = factor3_waves(nlo);
+    F.nxb = F.fB > 0 ? (n1 + F.fB - 1) / F.fB : 0;
+    F.nchunks = F.nxb * F.nlines;
+    // the generic kernel needs every row at once: the window is the grid
+    F.ring_rows = F.fB > 0 ? ring_rows_for(F, F.ldl) : n;
+    F.sBX = 8;
+    F.snxb = (n1 + F.sBX - 1) / F.sBX;
+    F.L = F.Ut = nullptr;
+    F.L32 = F.Ut32 = nullptr;
+    F.A64 = F.has64 ? c.take<double>((size_t)nlo * F.ldo) : nullptr;
+    F.A32 = F.has32 ? c.take<float>((size_t)nlo * F.ldo) : nullptr;
+    F.ring = c.take<double>((size_t)(F.ring_rows + 1) * F.ldl);
+    F.Dg = c.take<double>(n);
+    F.invD = c.take<double>(n);
+    F.invD32 = F.has32 ? c.take<float>(n) : nullptr;
+    F.d_offs = c.take<int>((size_t)4 * (nlo + 1));
+    F.prog = c.take<unsigned>((size_t)F.nlines);
+    F.ticket = c.take<unsigned>(4);
+    F.flag = c.take<int>(4);
+    F.coefA = c.take<double>((size_t)3 * tp);
+    F.coefB = c.take<double>(tp);
+    F.band = c.take<double>((size_t)2 * T1 * n1 * W);
+    F.fold3 = c.take<double>((size_t)F.nlines * W * W * 2 * T1);
+    F.steps = c.take<int>((size_t)4 * (nlo + 1));
+    F.sdxyz = c.take<int>(nlo + 1);
+    F.pairw = c.take<unsigned>((size_t)F.npairs + 64 * kPairsPerLane);
+    // packets: at most one per 64 pairs of each step, plus one per step
+    F.pk = c.take<int>((size_t)4 * ((size_t)F.npairs / (64 * kPairsPerLane) + 2 * (size_t)nlo + 2));
+    F.chunk_order = c.take<int>(F.nchunks > 0 ? F.nchunks : 1);
+    F.chunk_rank = c.take<int>(F.nchunks > 0 ? F.nchunks : 1);
+    F.blk_order = c.take<int>((size_t)F.nlines * F.snxb);
+    F.own = c.take<int>(16);
+    // generic-kernel fallback: level order of the rows and per-row done flags
+    {
+        const int64_t A1 = F.Hx + 1, B1 = (int64_t)(F.Hx + 1) * (F.Hy + 1);
+        F.maxlev = (int)((n1 - 1) * (1 + A1 + B1) + 1);
+    }
+    F.lev = c.take<int>((size_t)2 * F.maxlev + 2);
+    F.line_order = c.take<int>(F.fB > 0 ? 1 : n);   // row order of the generic kernel
+    F.pair_ptr = c.take<int>((size_t)2 * (nlo + 1));   // pair ranges per offset (chunked) / CSR (generic)
+    F.pair_j = c.take<int>(F.fB > 0 ? 1 : std::max(F.npairs, 1));
+    F.pair_l = c.take<int>(F.fB > 0 ? 1 : std::max(F.npairs, 1));
+    F.y_tmp = c.take<double>(n);   // precond_apply intermediate; generic kernel: done flags
+    F.runs = nullptr;
+    F.bytes = c.off + 256;
+    return F.bytes;
+}
+
+// ---------------------------------------------------------- kernels ------
+__global__ void reset3_kernel(unsigned* p, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+__global__ void fill_rows_kernel(double* __restrict__ ring, int64_t first, int64_t rows, int ldl, double v) {
+    const int64_t total = rows * ldl;
+    double* p = ring + first * ldl;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
+struct F3Args {
+    int n1, nlo, ldl, T, h, lgB, nxb, npk, j0;
+    int64_t n, ring_rows, ldo;
+    int tk_begin, tk_end;
+    const int4* pk;          // packets {first pair, count, packed (dx,dy,dz), j | first << 30 | last << 31}
+    const int2* jrange;      // [nlo] pair range of the step of offset j
+    const int4* offs;        // [nlo + 1] (dx, dy, dz, linear) in column order
+    const unsigned* pairw;   // [npairs + 64 Q] k*8 | (l*8) << 16
+    const int* chunk_order;
+    const int* chunk_base;   // [nchunks] (rank * B) mod ring_rows: first ring slot of the chunk
+    const double* band;
+    const double* fold;
+    double* ring;
+    double* A64;
+    float* A32;
+    double* Dg;
+    double* invD;
+    float* invD32;
+    unsigned* ticket;
+    int* flag;
+};
+
+// ring row of row (rx, line rl): its chunk's first slot plus rx mod B
+__device__ inline int64_t ring_slot(const F3Args& a, int rl, int rx) {
+    const int ch = rl * a.nxb + (rx >> a.lgB);
+    return (int64_t)a.chunk_base[ch] + (rx & ((1 << a.lgB) - 1));
+}
+
+// Q pairs per lane per packet (packets of up to 64 Q pairs), PP packets in flight
+template <int Q, int PP>
+__global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
+    extern __shared__ double smem3[];
+    __shared__ int s_chunk, s_rank;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n1 = a.n1, nlo = a.nlo, h = a.h;
+    const int W = 2 * h + 1, T1 = a.T + 1, bandT = n1 * W;
+    const int B = 1 << a.lgB;
+    double* u = smem3 + (size_t)wv * (nlo + 2);
+    const char* ub = (const char*)u;
+    const int64_t zbase = a.ring_rows * (int64_t)a.ldl;   // the zero row
+    // lanes past a packet's pairs: u index nlo+1 (zero) and the first step's
+    // entry of the same row (published together with the needed ones)
+    const unsigned padw = (unsigned)(nlo + 1) * 8u | ((unsigned)a.j0 * 8u << 16);
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned tk = atomicAdd(a.ticket, 1u);
+            const int t = a.tk_begin + (int)tk;
+            s_chunk = (t < a.tk_end) ? a.chunk_order[t] : -1;
+            s_rank = t;
+        }
+        __syncthreads();
+        const int chunk = s_chunk;
+        if (chunk < 0) break;
+        const int line = chunk / a.nxb;
+        const int ix = (chunk - line * a.nxb) * B + wv;
+        if (ix >= n1) continue;   // wave-uniform
+        const int iy = line % n1, iz = line / n1;
+        const int64_t i = (int64_t)line * n1 + ix;
+        const int64_t myslot = (int64_t)a.chunk_base[chunk] + wv;
+
+        // M(i, i + delta_k) for the lower offsets and the diagonal (Kronecker
+        // form of Sec. 4.2 over the folded line coefficients); zero where the
+        // column leaves the grid
+        for (int k = lane; k <= nlo; k += 64) {
+            const int4 o = a.offs[k];
+            double v = 0.0;
+            if ((unsigned)(ix + o.x) < (unsigned)n1 && (unsigned)(iy + o.y) < (unsigned)n1 &&
+                (unsigned)(iz + o.z) < (unsigned)n1) {
+                const double* pS = a.band + ix * W + (o.x + h);
+                const double* pF = a.fold + ((int64_t)line * W * W + (int64_t)(o.z + h) * W + (o.y + h)) * 2 * T1;
+                for (int t = 0; t < T1; ++t) v += pS[t * bandT] * pF[t] + pS[(T1 + t) * bandT] * pF[T1 + t];
+            }
+            u[k] = v;
+        }
+        if (lane == 0) u[nlo + 1] = 0.0;
+
+        double g[PP][Q];
+        unsigned pw[PP][Q];
+        int jj[PP], lastp[PP];
+        int64_t rb[PP];
+        int64_t cur = zbase;   // ring row offset of the step being issued
+        auto issue = [&](int b, int p) {
+            if (p >= a.npk) {   // wave-uniform: past the end
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    pw[b][q] = padw;
+                    g[b][q] = 0.0;
+                }
+                jj[b] = nlo + 1;
+                lastp[b] = 0;
+                rb[b] = zbase;
+                return;
+            }
+            const int4 P = a.pk[p];
+            if (P.w & (1 << 30)) {   // first packet of a step: its row
+                const int dx = (P.z & 0xFF) - 128, dy = ((P.z >> 8) & 0xFF) - 128, dz = ((P.z >> 16) & 0xFF) - 128;
+                const bool valid = (unsigned)(ix + dx) < (unsigned)n1 && (unsigned)(iy + dy) < (unsigned)n1 &&
+                                   (unsigned)(iz + dz) < (unsigned)n1;
+                cur = valid ? ring_slot(a, line + dy + dz * n1, ix + dx) * a.ldl : zbase;
+            }
+            rb[b] = cur;
+            jj[b] = P.w & 0x3FFFFFFF;
+            lastp[b] = (P.w >> 31) & 1;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int e = lane + 64 * q;
+                const unsigned wd0 = a.pairw[P.x + e];
+                pw[b][q] = (e < P.y) ? wd0 : padw;
+            }
+            const char* rowp = (const char*)(a.ring + cur);
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                g[b][q] = __hip_atomic_load((const double*)(rowp + (pw[b][q] >> 16)), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+        };
+        // the whole step again with coherent loads, until none of its values
+        // is the sentinel (a computed NaN ends the wait as well)
+        auto slow_step = [&](int j, int64_t base) {
+            const int2 R = a.jrange[j];
+            for (;;) {
+                bool pend = false;
+                double sum = 0.0;
+                for (int e0 = R.x; e0 < R.y || e0 == R.x; e0 += 64) {
+                    const int e = e0 + lane;
+                    const unsigned wd = (e < R.y) ? a.pairw[e] : padw;
+                    const double gv = ld_coh((const double*)((const char*)(a.ring + base) + (wd >> 16)));
+                    pend |= Sentinel<double>::is(gv);
+                    sum += *(const double*)(ub + (wd & 0xFFFFu)) * gv;
+                }
+                if (!__any(pend)) return wave_total_bcast(sum);
+                __builtin_amdgcn_s_sleep(2);
+            }
+        };
+        double acc = 0.0;
+        auto consume = [&](int b) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc += *(const double*)(ub + (pw[b][q] & 0xFFFFu)) * g[b][q];
+            if (lastp[b]) {   // wave-uniform
+                double tot = wave_total_bcast(acc);
+                acc = 0.0;
+                if (__builtin_expect(isnan(tot), 0)) tot = slow_step(jj[b], rb[b]);
+                const double mj = u[jj[b]];
+                if (lane == 0) u[jj[b]] = mj - tot;
+            }
+        };
+#pragma unroll
+        for (int b = 0; b < PP; ++b) issue(b, b);
+        for (int p0 = 0; p0 < a.npk; p0 += PP) {
+#pragma unroll
+            for (int b = 0; b < PP; ++b) {
+                if (p0 + b < a.npk) {   // wave-uniform
+                    consume(b);
+                    issue(b, p0 + b + PP);
+                }
+            }
+        }
+
+        // L(i, i+delta_k) = u_k / D(i+delta_k); D(i) = M(i,i) - sum_k u_k L(i, i+delta_k)
+        double piv = 0.0;
+        for (int k = lane; k < nlo; k += 64) {
+            const int4 o = a.offs[k];
+            double dv = 0.0;
+            if ((unsigned)(ix + o.x) < (unsigned)n1 && (unsigned)(iy + o.y) < (unsigned)n1 &&
+                (unsigned)(iz + o.z) < (unsigned)n1) {
+                const double* pd = a.ring + ring_slot(a, line + o.y + o.z * n1, ix + o.x) * a.ldl + nlo;
+                dv = *pd;
+                while (Sentinel<double>::is(dv)) {
+                    __builtin_amdgcn_s_sleep(2);
+                    dv = ld_coh(pd);
+                }
+            }
+            const double lk = u[k] * dv;
+            piv += u[k] * lk;
+            u[k] = lk;
+        }
+        piv = wave_total_bcast(piv);
+        const double Dr = u[nlo] - piv;
+        const double Dii = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(Dr)),
+                                            __builtin_amdgcn_readfirstlane(__double2loint(Dr)));
+        if (!(Dii > 0.0) || !isfinite(Dii)) {
+            if (lane == 0) atomicOr(a.flag, 1);
+        }
+        const double iv = 1.0 / Dii;
+        double* rowp = a.ring + myslot * a.ldl;
+        for (int k = lane; k < nlo; k += 64) {
+            const double lk = u[k];
+            st_coh(rowp + k, Sentinel<double>::clean(lk));
+            if (a.A64) a.A64[(int64_t)k * a.ldo + i] = lk;
+            if (a.A32) a.A32[(int64_t)k * a.ldo + i] = (float)lk;
+        }
+        if (lane == 0) {
+            st_coh(rowp + nlo, Sentinel<double>::clean(iv));
+            a.Dg[i] = Dii;
+            a.invD[i] = iv;
+            if (a.invD32) a.invD32[i] = (float)iv;
+        }
+    }
+}
+
+// generic-kernel output (row-major FP64 rows in the ring, 1/D at n_lower)
+// into the offset-major arrays
+__global__ void rows_to_offset_major_kernel(int64_t n, int nlo, int ldl, int64_t ldo, const double* __restrict__ R,
+                                            double* __restrict__ A64, float* __restrict__ A32,
+                                            float* __restrict__ invD32) {
+    __shared__ double tile[32][33];
+    const int64_t i0 = (int64_t)blockIdx.x * 32;
+    const int k0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = i0 + r;
+        const int k = k0 + tx;
+        tile[r][tx] = (i < n && k < nlo) ? R[i * ldl + k] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int k = k0 + r;
+        const int64_t i = i0 + tx;
+        if (k < nlo && i < n) {
+            const double v = tile[tx][r];
+            if (A64) A64[(int64_t)k * ldo + i] = v;
+            if (A32) A32[(int64_t)k * ldo + i] = (float)v;
+        }
+    }
+    if (blockIdx.y == 0 && invD32)
+        for (int r = threadIdx.x; r < 32; r += blockDim.x)
+            if (i0 + r < n) invD32[i0 + r] = (float)R[(i0 + r) * ldl + nlo];
+}
+
+// ------------------------------------------------------- substitutions ---
+template <typename T>
+struct S3Args {
+    int n1, nlo, nother, Hx, Hy, BX, nxb, nblk;
+    int64_t n, ldo;
+    const int4* offs;
+    const int* own;        // [16] index of offset (-m, 0, 0), m = 1..16, or -1
+    const int* blk_order;
+    const T* A;
+    const T* scale;        // 1/D for the backward substitution, else null
+    const T* in;
+    T* out;
+    unsigned* prog;
+    unsigned* ticket;
+    const int* stop;
+};
+
+// out[i'] = in[i'] * scale - sum_k L-term * out[i' + delta_k] in stream
+// coordinates (REV: the mirrored grid, i = n-1-i'); the L-term is
+// A[k][i] (forward) or A[k][i - delta_k] = A[k][mem(i' + delta_k)] (backward).
+template <typename T, bool REV>
+__global__ __launch_bounds__(256) void sweep3d_kernel(S3Args<T> a) {
+    constexpr int BXM = 8;                    // rows per block (a.BX == 8)
+    constexpr int NG = 256 / BXM;             // offset groups
+    constexpr int MO = 16;                    // in-line offsets (-m, 0, 0), m <= MO
+    __shared__ T s_part[NG][BXM];
+    __shared__ T s_coef[BXM][MO];
+    __shared__ T s_prev[MO + BXM];
+    __shared__ T s_rhs[BXM];
+    __shared__ int s_blk;
+    const int tid = threadIdx.x;
+    const int r = tid % BXM, grp = tid / BXM;
+    const int n1 = a.n1;
+    const int64_t n = a.n;
+    if (a.stop && *a.stop) return;
+    auto mem = [&](int64_t ip) -> int64_t { return REV ? (n - 1 - ip) : ip; };
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned tk = atomicAdd(a.ticket, 1u);
+            s_blk = (tk < (unsigned)a.nblk) ? a.blk_order[tk] : -1;
+        }
+        __syncthreads();
+        const int blk = s_blk;
+        if (blk < 0) break;
+        const int line = blk / a.nxb;
+        const int x0 = (blk - line * a.nxb) * BXM;
+        const int iy = line % n1, iz = line / n1;
+        // wait: own line up to x0, and the two lines that cover the others
+        if (tid == 0) {
+            const unsigned needo = (unsigned)min(n1, x0 + BXM + a.Hx);
+            if (x0 > 0) {
+                while (ld_coh(&a.prog[line]) < (unsigned)x0) __builtin_amdgcn_s_sleep(1);
+            }
+            if (iy > 0) {
+                while (ld_coh(&a.prog[line - 1]) < needo) __builtin_amdgcn_s_sleep(1);
+            }
+            if (iz > 0) {
+                const int l2 = (iz - 1) * n1 + min(iy + a.Hy, n1 - 1);
+                while (ld_coh(&a.prog[l2]) < needo) __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        const int ix = x0 + r;
+        const bool rowok = ix < n1;
+        const int64_t ip = (int64_t)line * n1 + (rowok ? ix : x0);
+        // terms of the other lines (offsets 0 .. nother-1 in column order)
+        T acc = T(0);
+        for (int k = grp; k < a.nother; k += NG) {
+            const int4 o = a.offs[k];
+            const bool ok = rowok && (unsigned)(ix + o.x) < (unsigned)n1 && (unsigned)(iy + o.y) < (unsigned)n1 &&
+                            (unsigned)(iz + o.z) < (unsigned)n1;
+            if (ok) {
+                const int64_t nb = mem(ip + o.w);
+                const T c = a.A[(int64_t)k * a.ldo + (REV ? nb : mem(ip))];
+                T v = __hip_atomic_load(&a.out[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                while (Sentinel<T>::is(v)) v = ld_coh(&a.out[nb]);
+                acc += c * v;
+            }
+        }
+        s_part[grp][r] = acc;
+        // in-line coefficients and the values of the preceding rows
+        if (tid < BXM * MO) {
+            const int rr = tid / MO, m = tid % MO;   // coefficient of (-(m+1), 0, 0) for row rr
+            const int k = a.own[m];
+            const int xx = x0 + rr;
+            T c = T(0);
+            if (k >= 0 && xx < n1 && xx - (m + 1) >= 0) {
+                const int64_t ipr = (int64_t)line * n1 + xx;
+                c = a.A[(int64_t)k * a.ldo + (REV ? mem(ipr - (m + 1)) : mem(ipr))];
+            }
+            s_coef[rr][m] = c;
+        } else if (tid < BXM * MO + MO) {
+            const int m = tid - BXM * MO;       // row x0 - MO + m
+            const int xx = x0 - MO + m;
+            T v = T(0);
+            if (xx >= 0) v = ld_coh(&a.out[mem((int64_t)line * n1 + xx)]);
+            s_prev[m] = v;
+        } else if (tid < BXM * MO + MO + BXM) {
+            const int rr = tid - BXM * MO - MO;
+            const int xx = x0 + rr;
+            T v = T(0);
+            if (xx < n1) {
+                const int64_t mm = mem((int64_t)line * n1 + xx);
+                v = a.in[mm];
+                if (a.scale) v *= a.scale[mm];
+            }
+            s_rhs[rr] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            T y[MO + BXM];
+#pragma unroll
+            for (int m = 0; m < MO; ++m) y[m] = s_prev[m];
+#pragma unroll
+            for (int rr = 0; rr < BXM; ++rr) {
+                T s = T(0);
+                for (int g2 = 0; g2 < NG; ++g2) s += s_part[g2][rr];
+                T v = s_rhs[rr] - s;
+#pragma unroll
+                for (int m = 0; m < MO; ++m) v -= s_coef[rr][m] * y[MO + rr - (m + 1)];
+                y[MO + rr] = v;
+            }
+#pragma unroll
+            for (int rr = 0; rr < BXM; ++rr) s_prev[rr] = y[MO + rr];   // results (reuses the buffer)
+        }
+        __syncthreads();
+        if (tid < BXM && x0 + tid < n1) {
+            st_coh(&a.out[mem((int64_t)line * n1 + x0 + tid)], Sentinel<T>::clean(s_prev[tid]));
+            wait_own_stores();
+        }
+        __syncthreads();
+        if (tid == 0) publish(&a.prog[line], (unsigned)min(n1, x0 + BXM));
+    }
+}
+
+template <typename T>
+__global__ void fill_sentinel3_kernel(int64_t n, T* __restrict__ out, const int* __restrict__ stop) {
+    if (stop && *stop) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = Sentinel<T>::value();
+}
+
+// ------------------------------------------------------------- host ------
+static int persistent_grid3(const void* kernel, int block, size_t shmem, int64_t units) {
+    int dev = 0, cus = 256, per = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, shmem) != hipSuccess || per < 1) per = 1;
+    int64_t g = (int64_t)cus * per;
+    if (g > units) g = units;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// order of units (x-block xb of line (iy, iz)) by key xb + wy iy + wz iz
+static void key_order(int n1, int nxb, const ChunkKeys& K, std::vector<int>& order, std::vector<int>* keys) {
+    const int nlines = n1 * n1;
+    const int64_t maxkey = (int64_t)(nxb - 1) + (int64_t)K.wy * (n1 - 1) + (int64_t)K.wz * (n1 - 1) + 1;
+    std::vector<int> cnt(maxkey + 1, 0);
+    for (int l = 0; l < nlines; ++l) {
+        const int64_t base = (int64_t)K.wy * (l % n1) + (int64_t)K.wz * (l / n1);
+        for (int xb = 0; xb < nxb; ++xb) cnt[base + xb + 1]++;
+    }
+    for (int64_t k = 0; k < maxkey; ++k) cnt[k + 1] += cnt[k];
+    if (keys) keys->assign(cnt.begin(), cnt.end());   // first rank of each key
+    order.assign((size_t)nlines * nxb, 0);
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int l = 0; l < nlines; ++l) {
+        const int64_t base = (int64_t)K.wy * (l % n1) + (int64_t)K.wz * (l / n1);
+        for (int xb = 0; xb < nxb; ++xb) order[fill[base + xb]++] = l * nxb + xb;
+    }
+}
+
+// Substitution tables: block order and the in-line offsets (-m, 0, 0).
+static lgp_status sweep3_tables(Factor& F, hipStream_t s, std::vector<int>& blk, std::vector<int>& own) {
+    const ChunkKeys K = chunk_keys(F.sBX, F.Hx, F.Hy, F.Hz);
+    key_order(F.n1, F.snxb, K, blk, nullptr);
+    own.assign(16, -1);
+    for (int k = 0; k < F.nlo; ++k) {
+        const int* o = &F.offs[3 * k];
+        if (o[1] == 0 && o[2] == 0 && o[0] < 0 && o[0] >= -16) own[-o[0] - 1] = k;
+    }
+    // the in-line offsets are the last ones of the lower list (column order)
+    int nin = 0;
+    for (int k = 0; k < F.nlo; ++k)
+        if (F.offs[3 * k + 1] == 0 && F.offs[3 * k + 2] == 0) ++nin;
+    for (int k = F.nlo - nin; k < F.nlo; ++k)
+        if (F.offs[3 * k + 1] != 0 || F.offs[3 * k + 2] != 0 || F.offs[3 * k] < -16) return LGP_E_UNSUPPORTED;
+    LGP_HIP(hipMemcpyAsync(F.blk_order, blk.data(), blk.size() * 4, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(F.own, own.data(), own.size() * 4, hipMemcpyHostToDevice, s));
+    return LGP_OK;
+}
+
+// ILU(0) of the 3D stencil with the chunked kernel. Preconditions: band
+// tables and folded coefficients computed, offsets, steps (dataflow order)
+// and pair words uploaded (pairw followed by 64 zero words). Synchronises
+// the stream before returning (the host tables go out of scope).
+lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hipEvent_t* ev) {
+    const int n1 = F.n1, nlo = F.nlo, B = F.fB;
+    if (B <= 0) return LGP_E_UNSUPPORTED;
+    const int nsteps = nlo;
+    constexpr int Q = kPairsPerLane;
+    // packets of at most 64 Q pairs, step by step in dataflow order:
+    // {first pair, count, packed (dx, dy, dz), j | first << 30 | last << 31}
+    std::vector<int> pk, jr(2 * (size_t)(nlo + 1), 0);
+    for (int st = 0; st < nsteps; ++st) {
+        const int j = st4[4 * st], p0 = st4[4 * st + 2], p1 = st4[4 * st + 3];
+        const int* o = &F.offs[3 * j];
+        const int packed = (o[0] + 128) | ((o[1] + 128) << 8) | ((o[2] + 128) << 16);
+        const int np = p1 - p0;
+        const int npk = std::max(1, (np + 64 * Q - 1) / (64 * Q));
+        for (int q = 0; q < npk; ++q) {
+            const unsigned fl = (unsigned)j | (q == 0 ? 1u << 30 : 0u) | (q == npk - 1 ? 1u << 31 : 0u);
+            pk.insert(pk.end(), {p0 + 64 * Q * q, std::max(0, std::min(64 * Q, np - 64 * Q * q)), packed, (int)fl});
+        }
+        jr[2 * j] = p0;
+        jr[2 * j + 1] = p1;
+    }
+    F.npk = (int)pk.size() / 4;
+    if ((size_t)F.npk > (size_t)F.npairs / (64 * Q) + 2 * (size_t)nlo + 2) return LGP_E_ARG;   // planner disagrees
+    // chunk order and ranks
+    const ChunkKeys K = chunk_keys(B, F.Hx, F.Hy, F.Hz);
+    std::vector<int> order, keystart, rank(F.nchunks);
+    key_order(n1, F.nxb, K, order, &keystart);
+    // first ring slot of each chunk: (rank * B) mod R (R is a multiple of B)
+    for (int t = 0; t < F.nchunks; ++t) rank[order[t]] = (int)(((int64_t)t * B) % F.ring_rows);
+    std::vector<int> blk, own;
+    lgp_status st0 = sweep3_tables(F, s, blk, own);
+    if (st0 != LGP_OK) return st0;
+    LGP_HIP(hipMemcpyAsync(F.pk, pk.data(), pk.size() * 4, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(F.chunk_order, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(F.chunk_rank, rank.data(), rank.size() * 4, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(F.pair_ptr, jr.data(), jr.size() * 4, hipMemcpyHostToDevice, s));
+    // launches: keys [k0, k1) with every row of keys [k0 - reach, k1) in R slots
+    const int nkeys = (int)keystart.size() - 1;
+    const int64_t R = F.ring_rows;
+    std::vector<std::pair<int, int>> launches;
+    for (int k0 = 0; k0 < nkeys;) {
+        const int lo = keystart[std::max(0, k0 - K.reach)];
+        int k1 = k0 + 1;
+        if ((int64_t)(keystart[k1] - lo) * B > R) return LGP_E_UNSUPPORTED;   // window smaller than the reach
+        while (k1 < nkeys && (int64_t)(keystart[k1 + 1] - lo) * B <= R) ++k1;
+        launches.push_back({keystart[k0], keystart[k1]});
+        k0 = k1;
+    }
+    // zero row, then per launch: sentinel into its slots, reset the ticket, run
+    hipLaunchKernelGGL(fill_rows_kernel, dim3(64), dim3(256), 0, s, F.ring, R, (int64_t)1, F.ldl, 0.0);
+    LGP_HIP(hipMemsetAsync(F.flag, 0, 16, s));
+    F3Args a;
+    a.n1 = n1;
+    a.nlo = nlo;
+    a.ldl = F.ldl;
+    a.T = F.T;
+    a.h = F.h;
+    a.lgB = 0;
+    while ((1 << a.lgB) < B) ++a.lgB;
+    a.nxb = F.nxb;
+    a.npk = F.npk;
+    a.j0 = st4[0];
+    a.n = F.n;
+    a.ring_rows = R;
+    a.ldo = F.ldo;
+    a.pk = (const int4*)F.pk;
+    a.jrange = (const int2*)F.pair_ptr;
+    a.offs = (const int4*)F.d_offs;
+    a.pairw = F.pairw;
+    a.chunk_order = F.chunk_order;
+    a.chunk_base = F.chunk_rank;
+    a.band = F.band;
+    a.fold = F.fold3;
+    a.ring = F.ring;
+    a.A64 = F.A64;
+    a.A32 = F.A32;
+    a.Dg = F.Dg;
+    a.invD = F.invD;
+    a.invD32 = F.invD32;
+    a.ticket = F.ticket;
+    a.flag = F.flag;
+    constexpr int PP = 2;
+    auto kf = ilu3d_factor_kernel<Q, PP>;
+    const size_t shmem = (size_t)B * (nlo + 2) * 8;
+    (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (ev) (void)hipEventRecord(ev[0], s);
+    for (auto& L : launches) {
+        const int64_t f0 = ((int64_t)L.first * B) % R, cnt = (int64_t)(L.second - L.first) * B;
+        const int64_t c1 = std::min(cnt, R - f0);
+        double sen;
+        {
+            const uint64_t bits = 0x7FF40000DEADBEEFull;   // the sentinel's bit pattern
+            memcpy(&sen, &bits, 8);
+        }
+        hipLaunchKernelGGL(fill_rows_kernel, dim3(4096), dim3(256), 0, s, F.ring, f0, c1, F.ldl, sen);
+        if (cnt > c1) hipLaunchKernelGGL(fill_rows_kernel, dim3(4096), dim3(256), 0, s, F.ring, (int64_t)0, cnt - c1, F.ldl, sen);
+        hipLaunchKernelGGL(reset3_kernel, dim3(1), dim3(64), 0, s, F.ticket, 4);
+        a.tk_begin = L.first;
+        a.tk_end = L.second;
+        const int grid = persistent_grid3((const void*)kf, 64 * B, shmem, L.second - L.first);
+        hipLaunchKernelGGL(kf, dim3(grid), dim3(64 * B), shmem, s, a);
+        LGP_CHECK_LAUNCH();
+    }
+    if (ev) (void)hipEventRecord(ev[1], s);
+    F.factor_kernel = 3;
+    LGP_HIP(hipStreamSynchronize(s));
+    return LGP_OK;
+}
+
+// After the generic kernel has written row-major FP64 rows into the ring
+// (ring_rows = n): offset-major arrays, FP32 pivots, substitution tables.
+// Synchronises the stream before returning.
+lgp_status factor3_generic_finish(Factor& F, hipStream_t s) {
+    std::vector<int> blk, own;
+    lgp_status st0 = sweep3_tables(F, s, blk, own);
+    if (st0 != LGP_OK) return st0;
+    const dim3 grid((unsigned)((F.n + 31) / 32), (unsigned)((F.nlo + 31) / 32));
+    hipLaunchKernelGGL(rows_to_offset_major_kernel, grid, dim3(256), 0, s, F.n, F.nlo, F.ldl, F.ldo,
+                       (const double*)F.ring, F.A64, F.A32, F.invD32);
+    LGP_CHECK_LAUNCH();
+    LGP_HIP(hipStreamSynchronize(s));
+    return LGP_OK;
+}
+
+template <typename T>
+static lgp_status sweep3_t(Factor& F, bool backward, const T* A, const T* scale, const T* in, T* out,
+                           hipStream_t s, const int* stop) {
+    if (!A) return LGP_E_UNSUPPORTED;
+    const int64_t n = F.n;
+    hipLaunchKernelGGL(reset3_kernel, dim3(std::min(1024, (F.nlines + 255) / 256 + 1)), dim3(256), 0, s, F.prog,
+                       F.nlines);
+    hipLaunchKernelGGL(reset3_kernel, dim3(1), dim3(64), 0, s, F.ticket + 2, 1);
+    hipLaunchKernelGGL(fill_sentinel3_kernel<T>, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)), dim3(256),
+                       0, s, n, out, stop);
+    int nin = 0;
+    for (int k = 0; k < F.nlo; ++k)
+        if (F.offs[3 * k + 1] == 0 && F.offs[3 * k + 2] == 0) ++nin;
+    S3Args<T> a;
+    a.n1 = F.n1;
+    a.nlo = F.nlo;
+    a.nother = F.nlo - nin;
+    a.Hx = F.Hx;
+    a.Hy = F.Hy;
+    a.BX = F.sBX;
+    a.nxb = F.snxb;
+    a.nblk = F.nlines * F.snxb;
+    a.n = n;
+    a.ldo = F.ldo;
+    a.offs = (const int4*)F.d_offs;
+    a.own = F.own;
+    a.blk_order = F.blk_order;
+    a.A = A;
+    a.scale = scale;
+    a.in = in;
+    a.out = out;
+    a.prog = F.prog;
+    a.ticket = F.ticket + 2;
+    a.stop = stop;
+    auto kf = backward ? sweep3d_kernel<T, true> : sweep3d_kernel<T, false>;
+    const int grid = persistent_grid3((const void*)kf, 256, 0, a.nblk);
+    hipLaunchKernelGGL(kf, dim3(grid), dim3(256), 0, s, a);
+    LGP_CHECK_LAUNCH();
+    return LGP_OK;
+}
+
+lgp_status sweep3(Factor& F, bool backward, bool lowp, const void* in, void* out, hipStream_t s, const int* stop) {
+    if (lowp) {
+        if (!F.A32) return LGP_E_UNSUPPORTED;
+        return sweep3_t<float>(F, backward, F.A32, backward ? F.invD32 : nullptr, (const float*)in, (float*)out, s,
+                               stop);
+    }
+    if (!F.A64) return LGP_E_UNSUPPORTED;
+    return sweep3_t<double>(F, backward, F.A64, backward ? F.invD : nullptr, (const double*)in, (double*)out, s,
+                            stop);
+}
+
+}  // namespace lgp

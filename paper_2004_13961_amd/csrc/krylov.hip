@@ -293,6 +293,7 @@ lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, con
     if (plan_ws(S, n, mixed, ws) > ws_bytes) return LGP_E_NOMEM;
     if (mixed && M.kind != 0) return LGP_E_UNSUPPORTED;
     if (mixed && !M.has32) return LGP_E_ARG;
+    if (!mixed && !M.has64) return LGP_E_UNSUPPORTED;   // factor kept in FP32 only
     lgp_status st;
     info->iters = 0;
     info->outer = 0;

@@ -160,10 +160,39 @@ struct Factor {
     double* ccPart = nullptr;  // [4*256 + 4] partial sums per field, then the means (c_b, c_a of z, y, x)
     double* y_tmp;    // [n] intermediate of precond_apply
     bool has32;
+    bool has64 = true;        // FP64 factor kept (FP64 solves possible)
     size_t bytes;
+    // d = 3: factor stored offset-major, A[k * ldo + i] = L(i, i + delta_k),
+    // so that both substitutions read it in contiguous runs of rows; rows
+    // are factored in an FP64 window (`ring`) of the rows still needed
+    int layout = 0;            // 0: row-major L (and Ut); 1: offset-major A64 / A32
+    int64_t ldo = 0;           // row stride of the offset-major arrays (>= n)
+    double* A64 = nullptr;     // [nlo][ldo], null when only FP32 is kept
+    float* A32 = nullptr;      // [nlo][ldo] FP32 copy for the inner sweeps
+    double* ring = nullptr;    // [ring_rows + 1][ldl] FP64 rows; the last one is zero
+    int64_t ring_rows = 0;
+    int fB = 0;                // rows per chunk (waves per workgroup) of the 3D factor, 0: generic kernel
+    int nxb = 0;               // chunks per grid line
+    int nchunks = 0;
+    int* chunk_order = nullptr;   // [nchunks] chunk ids in dependency order
+    int* chunk_rank = nullptr;    // [nchunks] position of each chunk in that order
+    int* pk = nullptr;            // [npk][4] packets of the steps' pair lists {step, first pair, count, last}
+    int npk = 0;
+    int sBX = 8;                  // rows per block of the 3D substitutions
+    int snxb = 0;                 // blocks per line
+    int* blk_order = nullptr;     // [nlines * snxb] substitution blocks in dependency order
+    int* own = nullptr;           // [8] offset index of (-m, 0, 0), m = 1..8 (-1 if absent)
+    double* fold3 = nullptr;      // folded line coefficients of the 3D path
 };
 
-size_t plan_factor(Factor& F, void* buf, bool with32);
+// storage requested for the factor (lgp_dtype values of the ABI)
+enum { STORE_F64 = 0, STORE_F64_F32 = 1, STORE_F32_ONLY = 3 };
+size_t plan_factor(Factor& F, void* buf, int store);
+size_t plan_factor3(Factor& F, void* buf, int store);
+lgp_status factor_build3(Factor& F, hipStream_t s, std::vector<int>& off4, std::vector<int>& st4,
+                         std::vector<int>& sd, std::vector<unsigned>& pw, hipEvent_t* ev);
+lgp_status sweep3(Factor& F, bool backward, bool lowp, const void* in, void* out, hipStream_t s,
+                  const int* stop);
 lgp_status factor_build(Factor& F, hipStream_t s);
 void factor_release(Factor& F);
 size_t const_factor_bytes(const Problem& P);

@@ -15,8 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblgpcg.so")
 
-LGP_F64, LGP_F32, LGP_BF16 = 0, 1, 2
-DTYPES = {"f64": LGP_F64, "f32": LGP_F32, "bf16": LGP_BF16}
+LGP_F64, LGP_F32, LGP_BF16, LGP_F32_ONLY = 0, 1, 2, 3
+DTYPES = {"f64": LGP_F64, "f32": LGP_F32, "bf16": LGP_BF16, "f32only": LGP_F32_ONLY}
 
 STATUS = {
     0: "LGP_OK", 1: "LGP_E_ARG", 2: "LGP_E_NOMEM", 3: "LGP_E_COEF", 4: "LGP_E_ILU_PIVOT",
@@ -30,7 +30,7 @@ EXPORTS = [
     "lgp_destroy_factor",
     "lgp_precond_apply", "lgp_ilu_forward", "lgp_ilu_backward", "lgp_factor_describe",
     "lgp_solve_workspace_bytes", "lgp_pcg_solve", "lgp_factor_const_bytes", "lgp_factor_const",
-    "lgp_pcg_solve_noalloc_max_bytes", "lgp_pcg_solve_noalloc",
+    "lgp_pcg_solve_noalloc_max_bytes", "lgp_pcg_solve_noalloc", "lgp_ilu_forward_f32", "lgp_ilu_backward_f32",
 ]
 
 
@@ -46,7 +46,8 @@ class FactorDesc(ctypes.Structure):
                 ("noff", ctypes.c_int), ("n_lower", ctypes.c_int),
                 ("offsets", ctypes.POINTER(ctypes.c_int)), ("L", ctypes.c_void_p),
                 ("D", ctypes.c_void_p), ("levels", ctypes.c_int), ("ld", ctypes.c_int),
-                ("factor_kernel_ms", ctypes.c_double), ("factor_kernel", ctypes.c_int)]
+                ("factor_kernel_ms", ctypes.c_double), ("factor_kernel", ctypes.c_int),
+                ("layout", ctypes.c_int), ("invD", ctypes.c_void_p)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -93,6 +94,8 @@ def lib():
         "lgp_precond_apply": (i32, [vp, vp, vp, vp]),
         "lgp_ilu_forward": (i32, [vp, vp, vp, vp]),
         "lgp_ilu_backward": (i32, [vp, vp, vp, vp]),
+        "lgp_ilu_forward_f32": (i32, [vp, vp, vp, vp]),
+        "lgp_ilu_backward_f32": (i32, [vp, vp, vp, vp]),
         "lgp_factor_describe": (i32, [vp, ctypes.POINTER(FactorDesc)]),
         "lgp_solve_workspace_bytes": (sz, [vp, i32]),
         "lgp_pcg_solve": (i32, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts), vp, sz, vp,

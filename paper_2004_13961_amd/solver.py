@@ -144,6 +144,20 @@ class Factor:
         check(lib().lgp_ilu_backward(self.handle, _ptr(y), _ptr(z), _stream()), "lgp_ilu_backward")
         return z
 
+    def forward32(self, r: torch.Tensor, y: torch.Tensor = None) -> torch.Tensor:
+        """y = L^{-1} r in FP32 on the factor's FP32 copy."""
+        _need(r, torch.float32, self.problem.n, "r")
+        y = torch.empty_like(r) if y is None else y
+        check(lib().lgp_ilu_forward_f32(self.handle, _ptr(r), _ptr(y), _stream()), "lgp_ilu_forward_f32")
+        return y
+
+    def backward32(self, y: torch.Tensor, z: torch.Tensor = None) -> torch.Tensor:
+        """z = U^{-1} y in FP32 on the factor's FP32 copy."""
+        _need(y, torch.float32, self.problem.n, "y")
+        z = torch.empty_like(y) if z is None else z
+        check(lib().lgp_ilu_backward_f32(self.handle, _ptr(y), _ptr(z), _stream()), "lgp_ilu_backward_f32")
+        return z
+
     def describe(self):
         """Pattern (offsets, n_lower) and views of the factor storage."""
         dsc = lgpcg.FactorDesc()
@@ -151,11 +165,19 @@ class Factor:
         offs = [(dsc.offsets[3 * k], dsc.offsets[3 * k + 1], dsc.offsets[3 * k + 2]) for k in range(dsc.noff)]
         n, nlo, ld = dsc.n, dsc.n_lower, dsc.ld
         base = self.buf.data_ptr()
-        rows = self.buf[dsc.L - base: dsc.L - base + n * ld * 8].view(torch.float64).view(n, ld)
         Dv = self.buf[dsc.D - base: dsc.D - base + n * 8].view(torch.float64)
-        return dict(offsets=offs, n_lower=nlo, ld=ld, L=rows[:, :nlo], invD=rows[:, nlo], D=Dv,
+        iv = self.buf[dsc.invD - base: dsc.invD - base + n * 8].view(torch.float64)
+        if dsc.layout == 1:
+            # offset-major: L[k * ld + i] = L(i, i + offset_k); an (n, n_lower) strided view
+            Lv = None
+            if dsc.L:
+                Lv = self.buf[dsc.L - base: dsc.L - base + nlo * ld * 8].view(torch.float64).view(nlo, ld)[:, :n].t()
+        else:
+            rows = self.buf[dsc.L - base: dsc.L - base + n * ld * 8].view(torch.float64).view(n, ld)
+            Lv = rows[:, :nlo]
+        return dict(offsets=offs, n_lower=nlo, ld=ld, L=Lv, invD=iv, D=Dv,
                     levels=dsc.levels, n=n, factor_kernel_ms=dsc.factor_kernel_ms,
-                    factor_kernel=dsc.factor_kernel)
+                    factor_kernel=dsc.factor_kernel, layout=dsc.layout)
 
 
 def pcg_solve(problem: Problem, factor: Factor, F: torch.Tensor, x: torch.Tensor = None, rtol: float = 1e-10,

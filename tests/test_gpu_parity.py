@@ -301,3 +301,57 @@ def test_non_finite_inputs_rejected(where, value):
     (F if where == "F" else x0)[7] = value
     x, info = pcg_solve(P, M, _dev(F), x=_dev(x0), rtol=1e-10, raise_on_error=False)
     assert info["status"] == "LGP_E_ARG", info
+
+
+@pytest.mark.parametrize("ring_rows", [0, 2000, 1700])
+def test_3d_factor_window(ring_rows, monkeypatch):
+    """3D factor through an FP64 window of recent rows: with the window cut
+    down to 2000 and 1700 rows (LGP_RING_ROWS) the factorisation runs as
+    several launches that reuse the window's slots; L, D and both
+    substitutions still match the oracle's Alg. 2-4 entry by entry."""
+    from paper_2004_13961_amd.solver import Factor, Problem
+    from paper_2004_13961_amd.workload import family_nodal
+    d, N, T, seed = 3, 16, 4, 3
+    print("case 3d window N=%d T=%d ring_rows=%d" % (N, T, ring_rows), flush=True)
+    if ring_rows:
+        monkeypatch.setenv("LGP_RING_ROWS", str(ring_rows))
+    B = gk.Basis(N)
+    c = synth.coefficient_draws(d, 6, seed)
+    a_o, b_o = owl.coefficient_a(c, B.x), owl.coefficient_b(d, B.x)
+    st, offs = _oracle_factor(d, N, a_o, b_o, T, T)
+    a_g, b_g, _, _ = family_nodal(d, N, 6, seed, with_rhs=False)
+    P = Problem(d, N, _dev(a_g).reshape(-1), _dev(b_g).reshape(-1))
+    M = Factor(P, T, store="f32")
+    desc = M.describe()
+    assert desc["layout"] == 1 and desc["factor_kernel"] == 3
+    nlo = desc["n_lower"]
+    Lo, Do = st.H[:, :nlo], st.H[:, nlo]
+    assert np.max(np.abs(_host(desc["L"]) - Lo)) <= 1e-12 * max(1.0, np.max(np.abs(Lo)))
+    assert np.max(np.abs(_host(desc["D"]) - Do)) <= 1e-12 * np.max(np.abs(Do))
+    r = synth.random_vector((N - 1) ** d, 77)
+    assert_entrywise(_host(M.forward(_dev(r))), st.forward(r), 1e-12, label="forward")
+    assert_entrywise(_host(M.backward(_dev(r))), st.backward(r), 1e-12, label="backward")
+
+
+def test_3d_fp32_only_factor():
+    """store = FP32 only (d = 3): the mixed solves give bit for bit what the
+    FP64+FP32 factor gives (same FP64 factorisation, same FP32 rounding of
+    it), and an FP64 solve with it is refused (LGP_E_UNSUPPORTED)."""
+    from paper_2004_13961_amd.solver import Factor, Problem, pcg_solve
+    from paper_2004_13961_amd.workload import family_nodal
+    d, N, T, seed = 3, 14, 4, 2
+    a_g, b_g, f_g, _ = family_nodal(d, N, 6, seed)
+    P = Problem(d, N, _dev(a_g).reshape(-1), _dev(b_g).reshape(-1))
+    Fg = P.load_vector(_dev(f_g).reshape(-1))
+    M_both = Factor(P, T, store="f32")
+    M_only = Factor(P, T, store="f32only")
+    assert M_only.describe()["L"] is None
+    assert M_only.buf.numel() < M_both.buf.numel()
+    for inner in ("f32", "bf16"):
+        x1, i1 = pcg_solve(P, M_both, Fg, rtol=1e-10, inner=inner)
+        x2, i2 = pcg_solve(P, M_only, Fg, rtol=1e-10, inner=inner)
+        assert i1["iters"] == i2["iters"] and i1["outer"] == i2["outer"]
+        assert torch.equal(x1, x2)
+        assert i2["relres_true"] <= 1e-10
+    x, info = pcg_solve(P, M_only, Fg, rtol=1e-10, raise_on_error=False)
+    assert info["status"] == "LGP_E_UNSUPPORTED"

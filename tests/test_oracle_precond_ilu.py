@@ -280,3 +280,46 @@ def test_many_rows_entries_match_row_by_row(d, N, T, seed):
         assert np.max(np.abs(out[t] - o1)) <= 1e-14 * scale
         assert np.max(np.abs(mag[t] - m1)) <= 1e-14 * scale
         assert np.max(np.abs(pmag[t] - p1)) <= 1e-14 * max(np.max(p1), 1e-300)
+
+
+def test_stencil_rows_plane_prefix():
+    """The first z-planes of the stencil rows equal the prefix of the full
+    array, and the oracle's ILU(0) of that prefix equals the prefix of the
+    full factorisation (rows only read earlier rows)."""
+    import synth
+    from oracle import galerkin as gk
+    from oracle import ilu as oilu
+    from oracle import precond as pc
+    from oracle import workload as owl
+    d, N, T = 3, 9, 3
+    n1 = N - 1
+    B = gk.Basis(N)
+    c = synth.coefficient_draws(d, 6, 4)
+    ah, bh = pc.series_pair(owl.coefficient_a(c, B.x), owl.coefficient_b(d, B.x), B, T, T)
+    offs = pc.stencil_offsets(ah, bh)
+    H = pc.stencil_rows(d, n1, ah, bh, offs)
+    Hp = pc.stencil_rows(d, n1, ah, bh, offs, nplanes=3)
+    assert Hp.shape == (3 * n1 * n1, len(offs))
+    assert np.array_equal(Hp, H[: 3 * n1 * n1])
+    full = oilu.StencilILU(d, n1, offs, H).factor()
+    part = oilu.StencilILU(d, n1, offs, Hp).factor(nrows=3 * n1 * n1)
+    assert np.array_equal(part.H, full.H[: 3 * n1 * n1])
+
+
+def test_forward_prefix_matches_full():
+    """Alg. 3 over a prefix of the rows gives the prefix of the full result."""
+    import synth
+    from oracle import galerkin as gk
+    from oracle import ilu as oilu
+    from oracle import precond as pc
+    from oracle import workload as owl
+    d, N, T = 3, 9, 3
+    n1 = N - 1
+    B = gk.Basis(N)
+    c = synth.coefficient_draws(d, 6, 4)
+    ah, bh = pc.series_pair(owl.coefficient_a(c, B.x), owl.coefficient_b(d, B.x), B, T, T)
+    offs = pc.stencil_offsets(ah, bh)
+    st = oilu.StencilILU(d, n1, offs, pc.stencil_rows(d, n1, ah, bh, offs)).factor()
+    r = synth.random_vector(n1 ** d, 5)
+    y, yp = st.forward(r), st.forward_prefix(r, 100)
+    assert np.array_equal(y[:100], yp[:100]) and not np.any(yp[100:])
