@@ -82,20 +82,18 @@ static int factor3_waves(int nlo) {
     return B;
 }
 
-static int64_t ring_rows_for(const Factor& F, int64_t ldl) {
-    // at most 24 GiB of FP64 rows, never more than one slot per row of every
-    // chunk (nchunks * B >= n); LGP_RING_ROWS lowers it (tests of the
-    // windowed path on small grids)
-    int64_t R = (int64_t)((24ull << 30) / ((uint64_t)ldl * 8ull)) - 1;
-    const int64_t all = (int64_t)F.nchunks * F.fB;
-    if (R > all) R = all;
-    if (const char* e = std::getenv("LGP_RING_ROWS")) {
+// FP64 window of the chunked kernel: Z whole z-planes of rows, row
+// (ix, iy, iz) in slot ((iz mod Z) n1 + iy) n1 + ix; at most 64 GiB, never
+// more than the grid; LGP_RING_PLANES lowers it (tests of the windowed path)
+static int ring_planes_for(const Factor& F, int64_t ldl) {
+    const int64_t plane = (int64_t)F.n1 * F.n1 * ldl * 8;
+    int64_t Z = (int64_t)(64ull << 30) / plane;
+    if (Z > F.n1) Z = F.n1;
+    if (const char* e = std::getenv("LGP_RING_PLANES")) {
         const long long v = std::atoll(e);
-        if (v > 0 && v < R) R = v;
+        if (v > 0 && v < Z) Z = v;
     }
-    // a whole number of chunks, so a chunk's slots never wrap
-    if (F.fB > 0) R = (R / F.fB) * F.fB;
-    return R;
+    return (int)Z;
 }
 
 size_t plan_factor3(Factor& F, void* buf, int store) {
@@ -113,7 +111,8 @@ size_t plan_factor3(Factor& F, void* buf, int store) {
     F.nxb = F.fB > 0 ? (n1 + F.fB - 1) / F.fB : 0;
     F.nchunks = F.nxb * F.nlines;
     // the generic kernel needs every row at once: the window is the grid
-    F.ring_rows = F.fB > 0 ? ring_rows_for(F, F.ldl) : n;
+    F.ring_planes = F.fB > 0 ? ring_planes_for(F, F.ldl) : n1;
+    F.ring_rows = (int64_t)F.ring_planes * n1 * n1;
     F.sBX = 8;
     F.snxb = (n1 + F.sBX - 1) / F.sBX;
     F.L = F.Ut = nullptr;
@@ -138,7 +137,6 @@ size_t plan_factor3(Factor& F, void* buf, int store) {
     // packets: at most one per 64 pairs of each step, plus one per step
     F.pk = c.take<int>((size_t)4 * ((size_t)F.npairs / (64 * kPairsPerLane) + 2 * (size_t)nlo + 2));
     F.chunk_order = c.take<int>(F.nchunks > 0 ? F.nchunks : 1);
-    F.chunk_rank = c.take<int>(F.nchunks > 0 ? F.nchunks : 1);
     F.blk_order = c.take<int>((size_t)F.nlines * F.snxb);
     F.own = c.take<int>(16);
     // generic-kernel fallback: level order of the rows and per-row done flags
@@ -162,6 +160,23 @@ __global__ void reset3_kernel(unsigned* p, int count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
+// sentinel into the window slots of the rows of chunks order[t0 .. t1)
+__global__ void fill_chunk_rows_kernel(double* __restrict__ ring, const int* __restrict__ order, int t0, int t1,
+                                       int B, int nxb, int n1, int Z, int ldl, double v) {
+    const int64_t per = (int64_t)B * ldl;
+    const int64_t total = (int64_t)(t1 - t0) * per;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int ch = order[t0 + (int)(e / per)];
+        const int rem = (int)(e % per);
+        const int b = rem / ldl, col = rem - b * ldl;
+        const int line = ch / nxb;
+        const int ix = (ch - line * nxb) * B + b;
+        if (ix >= n1) continue;
+        const int iz = line / n1, iy = line - iz * n1;
+        ring[(((int64_t)(iz % Z) * n1 + iy) * n1 + ix) * ldl + col] = v;
+    }
+}
+
 __global__ void fill_rows_kernel(double* __restrict__ ring, int64_t first, int64_t rows, int ldl, double v) {
     const int64_t total = rows * ldl;
     double* p = ring + first * ldl;
@@ -172,13 +187,13 @@ __global__ void fill_rows_kernel(double* __restrict__ ring, int64_t first, int64
 struct F3Args {
     int n1, nlo, ldl, T, h, lgB, nxb, npk, j0;
     int64_t n, ring_rows, ldo;
+    int ring_planes;
     int tk_begin, tk_end;
     const int4* pk;          // packets {first pair, count, packed (dx,dy,dz), j | first << 30 | last << 31}
     const int2* jrange;      // [nlo] pair range of the step of offset j
     const int4* offs;        // [nlo + 1] (dx, dy, dz, linear) in column order
     const unsigned* pairw;   // [npairs + 64 Q] k*8 | (l*8) << 16
     const int* chunk_order;
-    const int* chunk_base;   // [nchunks] (rank * B) mod ring_rows: first ring slot of the chunk
     const double* band;
     const double* fold;
     double* ring;
@@ -191,10 +206,10 @@ struct F3Args {
     int* flag;
 };
 
-// ring row of row (rx, line rl): its chunk's first slot plus rx mod B
+// ring row of row (rx, line rl = ry + n1 rz): ((rz mod Z) n1 + ry) n1 + rx
 __device__ inline int64_t ring_slot(const F3Args& a, int rl, int rx) {
-    const int ch = rl * a.nxb + (rx >> a.lgB);
-    return (int64_t)a.chunk_base[ch] + (rx & ((1 << a.lgB) - 1));
+    const int rz = rl / a.n1, ry = rl - rz * a.n1;
+    return ((int64_t)(rz % a.ring_planes) * a.n1 + ry) * a.n1 + rx;
 }
 
 // Q pairs per lane per packet (packets of up to 64 Q pairs), PP packets in flight
@@ -229,7 +244,7 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
         if (ix >= n1) continue;   // wave-uniform
         const int iy = line % n1, iz = line / n1;
         const int64_t i = (int64_t)line * n1 + ix;
-        const int64_t myslot = (int64_t)a.chunk_base[chunk] + wv;
+        const int64_t myslot = ring_slot(a, line, ix);
 
         // M(i, i + delta_k) for the lower offsets and the diagonal (Kronecker
         // form of Sec. 4.2 over the folded line coefficients); zero where the
@@ -252,6 +267,28 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
         int jj[PP], lastp[PP];
         int64_t rb[PP];
         int64_t cur = zbase;   // ring row offset of the step being issued
+        // packet descriptors, 64 at a time: lane t of `win` holds packet
+        // w0 + t, `nxt` the next 64 (loaded one window ahead); a descriptor
+        // is read with readlane, so the packet loop waits on no scalar load
+        int4 win, nxt;
+        int w0 = 0;
+        auto load_win = [&](int base) {
+            int4 v = make_int4(0, 0, 0, 0);
+            if (base + lane < a.npk) v = a.pk[base + lane];
+            return v;
+        };
+        win = load_win(0);
+        nxt = load_win(64);
+        auto desc = [&](int p) {
+            if (p >= w0 + 64) {   // wave-uniform: next window
+                w0 += 64;
+                win = nxt;
+                nxt = load_win(w0 + 64);
+            }
+            const int t = p - w0;
+            return make_int4(__builtin_amdgcn_readlane(win.x, t), __builtin_amdgcn_readlane(win.y, t),
+                             __builtin_amdgcn_readlane(win.z, t), __builtin_amdgcn_readlane(win.w, t));
+        };
         auto issue = [&](int b, int p) {
             if (p >= a.npk) {   // wave-uniform: past the end
 #pragma unroll
@@ -264,7 +301,7 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
                 rb[b] = zbase;
                 return;
             }
-            const int4 P = a.pk[p];
+            const int4 P = desc(p);
             if (P.w & (1 << 30)) {   // first packet of a step: its row
                 const int dx = (P.z & 0xFF) - 128, dy = ((P.z >> 8) & 0xFF) - 128, dz = ((P.z >> 16) & 0xFF) - 128;
                 const bool valid = (unsigned)(ix + dx) < (unsigned)n1 && (unsigned)(iy + dy) < (unsigned)n1 &&
@@ -403,6 +440,7 @@ __global__ void rows_to_offset_major_kernel(int64_t n, int nlo, int ldl, int64_t
 template <typename T>
 struct S3Args {
     int n1, nlo, nother, Hx, Hy, BX, nxb, nblk;
+    int offs_in_lds;
     int64_t n, ldo;
     const int4* offs;
     const int* own;        // [16] index of offset (-m, 0, 0), m = 1..16, or -1
@@ -419,12 +457,16 @@ struct S3Args {
 // out[i'] = in[i'] * scale - sum_k L-term * out[i' + delta_k] in stream
 // coordinates (REV: the mirrored grid, i = n-1-i'); the L-term is
 // A[k][i] (forward) or A[k][i - delta_k] = A[k][mem(i' + delta_k)] (backward).
-template <typename T, bool REV>
-__global__ __launch_bounds__(256) void sweep3d_kernel(S3Args<T> a) {
+// NT threads: BXM rows x NG offset groups; the offset table sits in LDS.
+template <typename T, bool REV, int NT>
+__global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
     constexpr int BXM = 8;                    // rows per block (a.BX == 8)
-    constexpr int NG = 256 / BXM;             // offset groups
+    constexpr int NG = NT / BXM;              // offset groups
     constexpr int MO = 16;                    // in-line offsets (-m, 0, 0), m <= MO
+    constexpr int U = 8;                      // terms in flight per thread
+    extern __shared__ int4 s_offs_lds[];      // [nother] when it fits LDS
     __shared__ T s_part[NG][BXM];
+    __shared__ T s_acc[BXM];
     __shared__ T s_coef[BXM][MO];
     __shared__ T s_prev[MO + BXM];
     __shared__ T s_rhs[BXM];
@@ -434,6 +476,9 @@ __global__ __launch_bounds__(256) void sweep3d_kernel(S3Args<T> a) {
     const int n1 = a.n1;
     const int64_t n = a.n;
     if (a.stop && *a.stop) return;
+    const int4* s_offs = a.offs_in_lds ? s_offs_lds : a.offs;
+    if (a.offs_in_lds)
+        for (int k = tid; k < a.nother; k += NT) s_offs_lds[k] = a.offs[k];
     auto mem = [&](int64_t ip) -> int64_t { return REV ? (n - 1 - ip) : ip; };
     for (;;) {
         __syncthreads();
@@ -465,20 +510,45 @@ __global__ __launch_bounds__(256) void sweep3d_kernel(S3Args<T> a) {
         const int ix = x0 + r;
         const bool rowok = ix < n1;
         const int64_t ip = (int64_t)line * n1 + (rowok ? ix : x0);
-        // terms of the other lines (offsets 0 .. nother-1 in column order)
-        T acc = T(0);
-        for (int k = grp; k < a.nother; k += NG) {
-            const int4 o = a.offs[k];
-            const bool ok = rowok && (unsigned)(ix + o.x) < (unsigned)n1 && (unsigned)(iy + o.y) < (unsigned)n1 &&
-                            (unsigned)(iz + o.z) < (unsigned)n1;
-            if (ok) {
-                const int64_t nb = mem(ip + o.w);
-                const T c = a.A[(int64_t)k * a.ldo + (REV ? nb : mem(ip))];
-                T v = __hip_atomic_load(&a.out[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                while (Sentinel<T>::is(v)) v = ld_coh(&a.out[nb]);
-                acc += c * v;
+        const int64_t mip = mem(ip);
+        // every value read here is final (the progress counters say so), but
+        // a cached line may still hold the sentinel (a NaN): the sum is formed
+        // first, and only a NaN sum is formed again with coherent re-reads.
+        // Loads are unconditional (a term outside the grid reads this row's
+        // own entries) and the term is selected away, so U terms are in flight.
+        auto terms = [&](bool coherent) {
+            T acc = T(0);
+            for (int k0 = grp; k0 < a.nother; k0 += NG * U) {
+                T cv[U], vv[U];
+                bool okv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int k = k0 + u * NG;
+                    const int4 o = s_offs[k < a.nother ? k : 0];
+                    const bool ok = k < a.nother && rowok && (unsigned)(ix + o.x) < (unsigned)n1 &&
+                                    (unsigned)(iy + o.y) < (unsigned)n1 && (unsigned)(iz + o.z) < (unsigned)n1;
+                    okv[u] = ok;
+                    const int64_t nb = ok ? mem(ip + o.w) : mip;
+                    const int kk = ok ? k : 0;
+                    cv[u] = a.A[(int64_t)kk * a.ldo + (REV ? nb : mip)];
+                    vv[u] = coherent ? ld_coh(&a.out[nb]) : a.out[nb];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (coherent) {
+                        const int k = k0 + u * NG;
+                        while (okv[u] && Sentinel<T>::is(vv[u])) {
+                            const int4 o = s_offs[k];
+                            vv[u] = ld_coh(&a.out[mem(ip + o.w)]);
+                        }
+                    }
+                    acc += okv[u] ? cv[u] * vv[u] : T(0);
+                }
             }
-        }
+            return acc;
+        };
+        T acc = terms(false);
+        if (__builtin_expect(isnan(acc), 0)) acc = terms(true);
         s_part[grp][r] = acc;
         // in-line coefficients and the values of the preceding rows
         if (tid < BXM * MO) {
@@ -509,15 +579,20 @@ __global__ __launch_bounds__(256) void sweep3d_kernel(S3Args<T> a) {
             s_rhs[rr] = v;
         }
         __syncthreads();
+        if (tid < BXM) {
+            T sum = T(0);
+#pragma unroll 8
+            for (int g2 = 0; g2 < NG; ++g2) sum += s_part[g2][tid];
+            s_acc[tid] = sum;
+        }
+        __syncthreads();
         if (tid == 0) {
             T y[MO + BXM];
 #pragma unroll
             for (int m = 0; m < MO; ++m) y[m] = s_prev[m];
 #pragma unroll
             for (int rr = 0; rr < BXM; ++rr) {
-                T s = T(0);
-                for (int g2 = 0; g2 < NG; ++g2) s += s_part[g2][rr];
-                T v = s_rhs[rr] - s;
+                T v = s_rhs[rr] - s_acc[rr];
 #pragma unroll
                 for (int m = 0; m < MO; ++m) v -= s_coef[rr][m] * y[MO + rr - (m + 1)];
                 y[MO + rr] = v;
@@ -622,30 +697,45 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
     if ((size_t)F.npk > (size_t)F.npairs / (64 * Q) + 2 * (size_t)nlo + 2) return LGP_E_ARG;   // planner disagrees
     // chunk order and ranks
     const ChunkKeys K = chunk_keys(B, F.Hx, F.Hy, F.Hz);
-    std::vector<int> order, keystart, rank(F.nchunks);
+    std::vector<int> order, keystart;
     key_order(n1, F.nxb, K, order, &keystart);
-    // first ring slot of each chunk: (rank * B) mod R (R is a multiple of B)
-    for (int t = 0; t < F.nchunks; ++t) rank[order[t]] = (int)(((int64_t)t * B) % F.ring_rows);
     std::vector<int> blk, own;
     lgp_status st0 = sweep3_tables(F, s, blk, own);
     if (st0 != LGP_OK) return st0;
     LGP_HIP(hipMemcpyAsync(F.pk, pk.data(), pk.size() * 4, hipMemcpyHostToDevice, s));
     LGP_HIP(hipMemcpyAsync(F.chunk_order, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
-    LGP_HIP(hipMemcpyAsync(F.chunk_rank, rank.data(), rank.size() * 4, hipMemcpyHostToDevice, s));
     LGP_HIP(hipMemcpyAsync(F.pair_ptr, jr.data(), jr.size() * 4, hipMemcpyHostToDevice, s));
-    // launches: keys [k0, k1) with every row of keys [k0 - reach, k1) in R slots
+    // launches: keys [k0, k1) such that the rows of keys [k0 - reach, k1)
+    // (all a launch writes or reads) span at most Z z-planes, so no two of
+    // them share a window slot
     const int nkeys = (int)keystart.size() - 1;
-    const int64_t R = F.ring_rows;
+    const int Z = F.ring_planes;
+    std::vector<int> zlo(nkeys, INT32_MAX), zhi(nkeys, -1);
+    for (int k = 0; k < nkeys; ++k)
+        for (int t = keystart[k]; t < keystart[k + 1]; ++t) {
+            const int iz = (order[t] / F.nxb) / n1;
+            zlo[k] = std::min(zlo[k], iz);
+            zhi[k] = std::max(zhi[k], iz);
+        }
+    auto span = [&](int klo, int khi) {   // z-planes of the rows of keys [klo, khi)
+        int lo = INT32_MAX, hi = -1;
+        for (int k = klo; k < khi; ++k) {
+            lo = std::min(lo, zlo[k]);
+            hi = std::max(hi, zhi[k]);
+        }
+        return hi < lo ? 0 : hi - lo + 1;
+    };
     std::vector<std::pair<int, int>> launches;
     for (int k0 = 0; k0 < nkeys;) {
-        const int lo = keystart[std::max(0, k0 - K.reach)];
+        const int lo = std::max(0, k0 - K.reach);
         int k1 = k0 + 1;
-        if ((int64_t)(keystart[k1] - lo) * B > R) return LGP_E_UNSUPPORTED;   // window smaller than the reach
-        while (k1 < nkeys && (int64_t)(keystart[k1 + 1] - lo) * B <= R) ++k1;
+        if (span(lo, k1) > Z) return LGP_E_UNSUPPORTED;   // window smaller than the reach
+        while (k1 < nkeys && span(lo, k1 + 1) <= Z) ++k1;
         launches.push_back({keystart[k0], keystart[k1]});
         k0 = k1;
     }
     // zero row, then per launch: sentinel into its slots, reset the ticket, run
+    const int64_t R = F.ring_rows;
     hipLaunchKernelGGL(fill_rows_kernel, dim3(64), dim3(256), 0, s, F.ring, R, (int64_t)1, F.ldl, 0.0);
     LGP_HIP(hipMemsetAsync(F.flag, 0, 16, s));
     F3Args a;
@@ -661,13 +751,13 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
     a.j0 = st4[0];
     a.n = F.n;
     a.ring_rows = R;
+    a.ring_planes = Z;
     a.ldo = F.ldo;
     a.pk = (const int4*)F.pk;
     a.jrange = (const int2*)F.pair_ptr;
     a.offs = (const int4*)F.d_offs;
     a.pairw = F.pairw;
     a.chunk_order = F.chunk_order;
-    a.chunk_base = F.chunk_rank;
     a.band = F.band;
     a.fold = F.fold3;
     a.ring = F.ring;
@@ -684,15 +774,13 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (ev) (void)hipEventRecord(ev[0], s);
     for (auto& L : launches) {
-        const int64_t f0 = ((int64_t)L.first * B) % R, cnt = (int64_t)(L.second - L.first) * B;
-        const int64_t c1 = std::min(cnt, R - f0);
         double sen;
         {
             const uint64_t bits = 0x7FF40000DEADBEEFull;   // the sentinel's bit pattern
             memcpy(&sen, &bits, 8);
         }
-        hipLaunchKernelGGL(fill_rows_kernel, dim3(4096), dim3(256), 0, s, F.ring, f0, c1, F.ldl, sen);
-        if (cnt > c1) hipLaunchKernelGGL(fill_rows_kernel, dim3(4096), dim3(256), 0, s, F.ring, (int64_t)0, cnt - c1, F.ldl, sen);
+        hipLaunchKernelGGL(fill_chunk_rows_kernel, dim3(4096), dim3(256), 0, s, F.ring, (const int*)F.chunk_order,
+                           L.first, L.second, B, F.nxb, n1, Z, F.ldl, sen);
         hipLaunchKernelGGL(reset3_kernel, dim3(1), dim3(64), 0, s, F.ticket, 4);
         a.tk_begin = L.first;
         a.tk_end = L.second;
@@ -755,9 +843,14 @@ static lgp_status sweep3_t(Factor& F, bool backward, const T* A, const T* scale,
     a.prog = F.prog;
     a.ticket = F.ticket + 2;
     a.stop = stop;
-    auto kf = backward ? sweep3d_kernel<T, true> : sweep3d_kernel<T, false>;
-    const int grid = persistent_grid3((const void*)kf, 256, 0, a.nblk);
-    hipLaunchKernelGGL(kf, dim3(grid), dim3(256), 0, s, a);
+    constexpr int NT = 512;
+    auto kf = backward ? sweep3d_kernel<T, true, NT> : sweep3d_kernel<T, false, NT>;
+    size_t shmem = (size_t)std::max(1, a.nother) * sizeof(int4);
+    a.offs_in_lds = shmem <= 96 * 1024;
+    if (!a.offs_in_lds) shmem = 16;
+    (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    const int grid = persistent_grid3((const void*)kf, NT, shmem, a.nblk);
+    hipLaunchKernelGGL(kf, dim3(grid), dim3(NT), shmem, s, a);
     LGP_CHECK_LAUNCH();
     return LGP_OK;
 }

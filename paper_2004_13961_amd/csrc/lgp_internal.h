@@ -170,7 +170,8 @@ struct Factor {
     double* A64 = nullptr;     // [nlo][ldo], null when only FP32 is kept
     float* A32 = nullptr;      // [nlo][ldo] FP32 copy for the inner sweeps
     double* ring = nullptr;    // [ring_rows + 1][ldl] FP64 rows; the last one is zero
-    int64_t ring_rows = 0;
+    int64_t ring_rows = 0;     // rows of the window (ring_planes whole z-planes)
+    int ring_planes = 0;
     int fB = 0;                // rows per chunk (waves per workgroup) of the 3D factor, 0: generic kernel
     int nxb = 0;               // chunks per grid line
     int nchunks = 0;

@@ -303,18 +303,18 @@ def test_non_finite_inputs_rejected(where, value):
     assert info["status"] == "LGP_E_ARG", info
 
 
-@pytest.mark.parametrize("ring_rows", [0, 2000, 1700])
-def test_3d_factor_window(ring_rows, monkeypatch):
+@pytest.mark.parametrize("ring_planes", [0, 12, 10])
+def test_3d_factor_window(ring_planes, monkeypatch):
     """3D factor through an FP64 window of recent rows: with the window cut
-    down to 2000 and 1700 rows (LGP_RING_ROWS) the factorisation runs as
-    several launches that reuse the window's slots; L, D and both
+    down to 12 and 10 of the 15 z-planes (LGP_RING_PLANES) the factorisation
+    runs as 2 and 6 launches that reuse the window's slots; L, D and both
     substitutions still match the oracle's Alg. 2-4 entry by entry."""
     from paper_2004_13961_amd.solver import Factor, Problem
     from paper_2004_13961_amd.workload import family_nodal
     d, N, T, seed = 3, 16, 4, 3
-    print("case 3d window N=%d T=%d ring_rows=%d" % (N, T, ring_rows), flush=True)
-    if ring_rows:
-        monkeypatch.setenv("LGP_RING_ROWS", str(ring_rows))
+    print("case 3d window N=%d T=%d ring_planes=%d" % (N, T, ring_planes), flush=True)
+    if ring_planes:
+        monkeypatch.setenv("LGP_RING_PLANES", str(ring_planes))
     B = gk.Basis(N)
     c = synth.coefficient_draws(d, 6, seed)
     a_o, b_o = owl.coefficient_a(c, B.x), owl.coefficient_b(d, B.x)
