@@ -289,13 +289,14 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
             return make_int4(__builtin_amdgcn_readlane(win.x, t), __builtin_amdgcn_readlane(win.y, t),
                              __builtin_amdgcn_readlane(win.z, t), __builtin_amdgcn_readlane(win.w, t));
         };
-        auto issue = [&](int b, int p) {
+        // Two stages per packet: A loads the descriptor's pair words and fixes
+        // the step's row (PT packets ahead), B gathers the row entries the
+        // pair words name (PG packets ahead), so neither stage waits on a
+        // load issued in the same iteration.
+        auto stage_a = [&](int b, int p) {
             if (p >= a.npk) {   // wave-uniform: past the end
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    pw[b][q] = padw;
-                    g[b][q] = 0.0;
-                }
+                for (int q = 0; q < Q; ++q) pw[b][q] = padw;
                 jj[b] = nlo + 1;
                 lastp[b] = 0;
                 rb[b] = zbase;
@@ -317,7 +318,9 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
                 const unsigned wd0 = a.pairw[P.x + e];
                 pw[b][q] = (e < P.y) ? wd0 : padw;
             }
-            const char* rowp = (const char*)(a.ring + cur);
+        };
+        auto stage_b = [&](int b) {
+            const char* rowp = (const char*)(a.ring + rb[b]);
 #pragma unroll
             for (int q = 0; q < Q; ++q)
                 g[b][q] = __hip_atomic_load((const double*)(rowp + (pw[b][q] >> 16)), __ATOMIC_RELAXED,
@@ -353,14 +356,18 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
                 if (lane == 0) u[jj[b]] = mj - tot;
             }
         };
+        constexpr int PG = PP / 2;   // gathers in flight (packets)
 #pragma unroll
-        for (int b = 0; b < PP; ++b) issue(b, b);
+        for (int b = 0; b < PP; ++b) stage_a(b, b);
+#pragma unroll
+        for (int b = 0; b < PG; ++b) stage_b(b);
         for (int p0 = 0; p0 < a.npk; p0 += PP) {
 #pragma unroll
             for (int b = 0; b < PP; ++b) {
                 if (p0 + b < a.npk) {   // wave-uniform
                     consume(b);
-                    issue(b, p0 + b + PP);
+                    stage_b((b + PG) % PP);        // packet p0 + b + PG
+                    stage_a(b, p0 + b + PP);
                 }
             }
         }
@@ -768,7 +775,7 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
     a.invD32 = F.invD32;
     a.ticket = F.ticket;
     a.flag = F.flag;
-    constexpr int PP = 2;
+    constexpr int PP = 4;
     auto kf = ilu3d_factor_kernel<Q, PP>;
     const size_t shmem = (size_t)B * (nlo + 2) * 8;
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
