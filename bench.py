@@ -231,6 +231,76 @@ def measured_traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
+def batched_throughput(count, log):
+    """`count` requests of the 2D N = 1024, T = 8 family (coefficient seeds 1,
+    2, ...): end to end one after another (each: operator, factor, load
+    vector, PCG to 1e-10), against the same requests with their PCG solves
+    run together as one batch (factors built one after another, then
+    lgp_pcg_solve_batched). Every batched result is checked equal, bit for
+    bit, to its solve alone."""
+    import torch
+
+    import synth
+    from paper_2004_13961_amd.solver import Factor, Problem, pcg_solve, pcg_solve_batched
+    from paper_2004_13961_amd.workload import family_nodal
+    cfg = synth.WORKLOADS["2d_N1024_T8"]
+    d, N, T = cfg.d, cfg.N, cfg.T
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v).reshape(-1)).cuda()
+    inputs = []
+    for k in range(count):
+        a, b, f, _ = family_nodal(d, N, cfg.J, cfg.seed + k)
+        inputs.append((dev(a), dev(b), dev(f)))
+    torch.cuda.synchronize()
+
+    def build(k):
+        a, b, f = inputs[k]
+        P = Problem(d, N, a, b)
+        M = Factor(P, T)
+        return P, M, P.load_vector(f)
+
+    # warm (tile choices, first launches)
+    P0, M0, F0 = build(0)
+    pcg_solve(P0, M0, F0, rtol=cfg.tol)
+    pcg_solve_batched([P0], [M0], [F0], rtol=cfg.tol)
+    del P0, M0, F0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    alone = []
+    for k in range(count):
+        P, M, F = build(k)
+        x, info = pcg_solve(P, M, F, rtol=cfg.tol)
+        alone.append((x, info))
+        del P, M, F
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    reqs = [build(k) for k in range(count)]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    xs, infos = pcg_solve_batched([r[0] for r in reqs], [r[1] for r in reqs], [r[2] for r in reqs], rtol=cfg.tol)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t1
+    t_batch = time.perf_counter() - t0
+    same = all(torch.equal(xb, xa[0]) and ib["iters"] == xa[1]["iters"] for xb, ib, xa in zip(xs, infos, alone))
+    # solve-only, one at a time on the same factors
+    t1 = time.perf_counter()
+    for P, M, F in reqs:
+        pcg_solve(P, M, F, rtol=cfg.tol)
+    torch.cuda.synchronize()
+    t_solve_seq = time.perf_counter() - t1
+    log("batch of %d (2d_N1024_T8): one by one %.1f ms, batched %.1f ms (setup %.1f + solves %.1f), "
+        "solves one by one %.1f ms, identical %s" % (count, t_seq * 1e3, t_batch * 1e3, t_setup * 1e3,
+                                                     t_solve * 1e3, t_solve_seq * 1e3, same))
+    del reqs, xs, alone, inputs
+    torch.cuda.empty_cache()
+    return {"workload": "2d_N1024_T8", "requests": count, "requests_per_sec_one_by_one": round(count / t_seq, 3),
+            "requests_per_sec_batched": round(count / t_batch, 3),
+            "solves_per_sec_one_by_one": round(count / t_solve_seq, 3),
+            "solves_per_sec_batched": round(count / t_solve, 3), "setup_ms": round(t_setup * 1e3, 2),
+            "batched_equal_to_alone": bool(same), "iters": [i["iters"] for i in infos]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +310,8 @@ def main():
                     help="3d_N256_T6_mixed (default), 3d_N128_T6, 2d_N1024_T8 or 2d_N32_T4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-lines", type=int, default=64)
+    ap.add_argument("--batch", type=int, default=8, help="requests of the batched-throughput section (0: skip)")
+    ap.add_argument("--only-extras", action="store_true", help="skip the main workload (batch / serving only)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="finish with one device-to-device copy of this many bytes (a reference "
                          "for hardware byte counters)")
@@ -255,6 +327,13 @@ def main():
     from paper_2004_13961_amd import lgpcg
     from paper_2004_13961_amd.solver import Factor, Problem, pcg_solve
     from paper_2004_13961_amd.workload import family_nodal
+
+    if args.only_extras:
+        extras = {}
+        if args.batch > 0:
+            extras["batched"] = batched_throughput(args.batch, log)
+        print(json.dumps(extras), flush=True)
+        return
 
     cfg = synth.WORKLOADS[args.workload]
     d, N, T = cfg.d, cfg.N, cfg.T
@@ -431,6 +510,8 @@ def main():
     }
     del state, P, M, F, x, u32, y32
     torch.cuda.empty_cache()
+    if args.batch > 0:
+        out["batched"] = batched_throughput(args.batch, log)
     if not args.no_cpu_baseline:
         log("oracle on the host CPU (bounded sample)")
         cb = cpu_baseline(cfg, args.cpu_sample_lines, max(1, it))

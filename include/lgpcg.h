@@ -259,6 +259,51 @@ lgp_status lgp_pcg_solve(lgp_problem p, lgp_factor m, const double* F, double* x
                          const lgp_solve_opts* opts, void* ws, size_t ws_bytes,
                          void* stream, lgp_solve_info* info);
 
+/* ----------------------------------------------------------- batches -- */
+/* Many requests of one grid shape (same d and N) solved together (Alg. 1 on
+ * each): every kernel of a PCG iteration covers all running requests in one
+ * launch -- the two substitutions of every request in one persistent launch,
+ * the vector updates and dot products with one block row per request -- and
+ * the iteration is captured once as a HIP graph and replayed while the set
+ * of running requests is unchanged (not on the null stream). Each request
+ * computes exactly what lgp_pcg_solve computes for it (FP64 PCG with the
+ * same restarts), so results equal the single-request ones bit for bit.
+ * Requests join and leave between steps (continuous batching): a slot is
+ * filled by lgp_batch_add, advanced by lgp_batch_step, read by
+ * lgp_batch_info and freed by lgp_batch_remove. Factors of one batch must
+ * share the pattern NZ(M) (same truncation and nonzero series terms);
+ * lgp_batch_add returns LGP_E_UNSUPPORTED for another pattern (it then
+ * needs its own batch) and LGP_E_NOMEM when every slot is taken. Only FP64
+ * solves (opts->inner = LGP_F64) are batched. The workspace (device,
+ * lgp_batch_workspace_bytes) is owned by the caller; problems, factors, F
+ * and x must stay alive while their slot is in use. Calls on one batch are
+ * ordered on its stream. */
+typedef struct lgp_batch_s* lgp_batch;
+size_t lgp_batch_workspace_bytes(lgp_problem shape, int slots);
+lgp_status lgp_batch_create(lgp_problem shape, int slots, void* ws, size_t ws_bytes, void* stream,
+                            lgp_batch* out);
+/* Admit a request: ||F||, the true residual of the initial guess x (device,
+ * in: x0, out: solution) and the first scalars, on the batch's stream
+ * (synchronises); *slot receives its slot. A request that needs no iteration
+ * (F = 0, or x0 already within rtol) or is rejected (non-finite F or x0) is
+ * finished at once (see lgp_batch_info). */
+lgp_status lgp_batch_add(lgp_batch b, lgp_problem p, lgp_factor m, const double* F, double* x,
+                         const lgp_solve_opts* opts, int* slot);
+/* `iters` PCG iterations of every running request, then the convergence
+ * check of each (true FP64 residual, restart up to 3 times); synchronises.
+ * *running: requests still running. */
+lgp_status lgp_batch_step(lgp_batch b, int iters, int* running);
+lgp_status lgp_batch_info(lgp_batch b, int slot, lgp_solve_info* info, int* finished);
+lgp_status lgp_batch_remove(lgp_batch b, int slot);
+void lgp_batch_destroy(lgp_batch b);
+/* All of the above for `count` requests at once: p, m, F, x host arrays of
+ * count handles / device pointers, info host array of count results; ws of
+ * lgp_batch_workspace_bytes(p[0], count) bytes. Returns the first non-OK
+ * status among the requests (each one's is in info). */
+lgp_status lgp_pcg_solve_batched(int count, const lgp_problem* p, const lgp_factor* m, const double* const* F,
+                                 double* const* x, const lgp_solve_opts* opts, void* ws, size_t ws_bytes,
+                                 void* stream, lgp_solve_info* info);
+
 /* ------------------------------------------------ allocation-free solve -- */
 /* For callers that cannot allocate device memory at solve time (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):

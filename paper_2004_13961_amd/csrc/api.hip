@@ -7,6 +7,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <vector>
 
 #include "lgp_internal.h"
 
@@ -564,6 +565,106 @@ lgp_status lgp_pcg_solve(lgp_problem p, lgp_factor m, const double* F, double* x
     return st;
 }
 
+
+// ------------------------------------------------------------ batches ----
+struct lgp_batch_s {
+    Batch* B;
+};
+
+static int nlines_of(const Problem& P) { return P.d == 3 ? P.n1 * P.n1 : (P.d == 2 ? P.n1 : 1); }
+
+static bool opts_from(const lgp_solve_opts* opts, lgp_solve_opts& o) {
+    o.rtol = 1e-10;
+    o.max_iter = 2000;
+    o.inner = LGP_F64;
+    o.inner_rtol = 0.0;
+    o.max_outer = 60;
+    o.check_every = 4;
+    if (opts) {
+        o = *opts;
+        if (!(o.rtol > 0.0)) return false;
+        if (o.max_iter <= 0) o.max_iter = 2000;
+        if (o.max_outer <= 0) o.max_outer = 60;
+        if (o.check_every <= 0) o.check_every = 4;
+    }
+    return o.inner == LGP_F64;
+}
+
+size_t lgp_batch_workspace_bytes(lgp_problem shape, int slots) {
+    if (!shape || slots < 1 || slots > 4096) return 0;
+    return batch_ws_bytes(shape->P.n, nlines_of(shape->P), slots);
+}
+
+lgp_status lgp_batch_create(lgp_problem shape, int slots, void* ws, size_t ws_bytes, void* stream, lgp_batch* out) {
+    if (!out) return LGP_E_ARG;
+    *out = nullptr;
+    if (!shape || !ws || slots < 1 || slots > 4096) return LGP_E_ARG;
+    lgp_status st = LGP_OK;
+    Batch* B = batch_create(shape->P, slots, ws, ws_bytes, (hipStream_t)stream, &st);
+    if (!B) return st;
+    lgp_batch_s* h = new (std::nothrow) lgp_batch_s{B};
+    if (!h) {
+        batch_destroy(B);
+        return LGP_E_NOMEM;
+    }
+    *out = h;
+    return LGP_OK;
+}
+
+lgp_status lgp_batch_add(lgp_batch b, lgp_problem p, lgp_factor m, const double* F, double* x,
+                         const lgp_solve_opts* opts, int* slot) {
+    if (!b || !p || !m || !F || !x || !slot) return LGP_E_ARG;
+    lgp_solve_opts o;
+    if (!opts_from(opts, o)) return opts && opts->inner != LGP_F64 ? LGP_E_UNSUPPORTED : LGP_E_ARG;
+    LGP_ONE_THREAD();
+    return batch_add(b->B, p->P, m->F, F, x, o, slot);
+}
+
+lgp_status lgp_batch_step(lgp_batch b, int iters, int* running) {
+    if (!b || iters < 0 || !running) return LGP_E_ARG;
+    LGP_ONE_THREAD();
+    return batch_step(b->B, iters, running);
+}
+
+lgp_status lgp_batch_info(lgp_batch b, int slot, lgp_solve_info* info, int* finished) {
+    if (!b || !info || !finished) return LGP_E_ARG;
+    return batch_info(b->B, slot, info, finished);
+}
+
+lgp_status lgp_batch_remove(lgp_batch b, int slot) {
+    if (!b) return LGP_E_ARG;
+    return batch_remove(b->B, slot);
+}
+
+void lgp_batch_destroy(lgp_batch b) {
+    if (!b) return;
+    batch_destroy(b->B);
+    delete b;
+}
+
+lgp_status lgp_pcg_solve_batched(int count, const lgp_problem* p, const lgp_factor* m, const double* const* F,
+                                 double* const* x, const lgp_solve_opts* opts, void* ws, size_t ws_bytes,
+                                 void* stream, lgp_solve_info* info) {
+    if (count < 1 || !p || !m || !F || !x || !ws || !info) return LGP_E_ARG;
+    for (int k = 0; k < count; ++k)
+        if (!p[k] || !m[k] || !F[k] || !x[k]) return LGP_E_ARG;
+    lgp_batch b = nullptr;
+    lgp_status st = lgp_batch_create(p[0], count, ws, ws_bytes, stream, &b);
+    if (st != LGP_OK) return st;
+    std::vector<int> slot(count, -1);
+    for (int k = 0; k < count && st == LGP_OK; ++k) st = lgp_batch_add(b, p[k], m[k], F[k], x[k], opts, &slot[k]);
+    const int every = (opts && opts->check_every > 0) ? opts->check_every : 4;
+    int running = 1;
+    while (st == LGP_OK && running > 0) st = lgp_batch_step(b, every, &running);
+    lgp_status worst = st;
+    for (int k = 0; k < count && st == LGP_OK; ++k) {
+        int fin = 0;
+        lgp_batch_info(b, slot[k], &info[k], &fin);
+        if (info[k].status != LGP_OK && worst == LGP_OK) worst = info[k].status;
+    }
+    lgp_batch_destroy(b);
+    return worst;
+}
 
 // ------------------------------------------------- allocation-free solve --
 // Workspace of lgp_pcg_solve_noalloc: one file-scope device array, one copy

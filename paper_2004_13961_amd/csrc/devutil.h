@@ -5,6 +5,14 @@
 
 namespace lgp {
 
+// Raise a kernel's dynamic LDS limit; skipped while `s` is being captured
+// into a graph (the attribute, set by an earlier eager launch, persists).
+inline void set_dyn_shmem(const void* kernel, size_t bytes, hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
+    (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 // ------------------------------------------------------ device helpers ---
 // Values produced and consumed inside one kernel by different workgroups
 // (substitution results, factor rows, pivots, progress flags) travel through

@@ -879,10 +879,11 @@ __device__ inline void pair_walk(int n1, int64_t n, int ldl, int first, int lbas
 
 template <typename T, int SL, int D, int NW, bool REV, bool SCALE>
 __global__ __launch_bounds__(64 * NW) void sweep2d_pair_kernel(int n1, int64_t n, int nlo, int ldl,
-                                                               const int4* __restrict__ offs, const T* __restrict__ A,
-                                                               const T* __restrict__ scale, const T* __restrict__ in,
-                                                               T* __restrict__ out, unsigned* ticket,
-                                                               const int* __restrict__ stop, int Hx, int Hy) {
+                                                               const int4* __restrict__ offs, const T* __restrict__ A0,
+                                                               const T* __restrict__ scale0, const T* __restrict__ in0,
+                                                               T* __restrict__ out0, unsigned* ticket,
+                                                               const int* __restrict__ stop, int Hx, int Hy,
+                                                               const SweepSlot<T>* __restrict__ slots, int nslots) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     T* lb = (T*)smem_raw;   // [Hy + B][n1 + 2 Hx] line buffers, then one zero slot
     __shared__ int s_band;
@@ -896,14 +897,33 @@ __global__ __launch_bounds__(64 * NW) void sweep2d_pair_kernel(int n1, int64_t n
     const int nl = Hy + B;
     const int zslot = nl * Wd;
     const int g = lane >> 5, j = lane & 31;
+    // batched: ticket t is band t / nslots of slot t % nslots, so each slot's
+    // bands are taken in order
+    const int ns = slots ? nslots : 1;
     for (;;) {
         if (tid == 0) {
             const unsigned tk = atomicAdd(ticket, 1u);
-            s_band = (tk < (unsigned)nbands) ? (int)tk : -1;
+            s_band = (tk < (unsigned)(nbands * ns)) ? (int)tk : -1;
         }
         __syncthreads();
-        const int band = __builtin_amdgcn_readfirstlane(s_band);
-        if (band < 0) break;
+        const int bt = __builtin_amdgcn_readfirstlane(s_band);
+        if (bt < 0) break;
+        const int band = bt / ns;
+        const T* A = A0;
+        const T* scale = scale0;
+        const T* in = in0;
+        T* out = out0;
+        if (slots) {
+            const SweepSlot<T> sl = slots[bt - band * ns];
+            if (sl.stop && *sl.stop) {   // this request has converged: its bands are skipped
+                __syncthreads();
+                continue;
+            }
+            A = sl.A;
+            scale = sl.scale;
+            in = sl.in;
+            out = sl.out;
+        }
         const int first = band * B;
         const int lbase = first - Hy;
         // lines above the grid and the Hx columns either side are zero; the
@@ -1795,7 +1815,8 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
             hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pair_shmem);
             const int grid = persistent_grid((const void*)kf, 64 * PNW, pair_shmem, nbands);
             hipLaunchKernelGGL(kf, dim3(grid), dim3(64 * PNW), pair_shmem, s, F.n1, n, F.nlo, F.ldl,
-                               (const int4*)F.d_offs, A, scale, in, out, tick, stop, F.Hx, F.Hy);
+                               (const int4*)F.d_offs, A, scale, in, out, tick, stop, F.Hx, F.Hy,
+                               (const SweepSlot<T>*)nullptr, 0);
         };
 #define LGP_PAIR(SLv)                                                                    \
     case SLv:                                                                            \
@@ -1840,6 +1861,48 @@ static lgp_status sweep_t(Factor& F, bool backward, const T* A, const T* scale, 
                            (const int*)F.line_order, F.nlines, F.Hx, F.Hy, A, scale, in, out, prog, tick,
                            stop);
     }
+    LGP_CHECK_LAUNCH();
+    return LGP_OK;
+}
+
+template <typename T>
+__global__ void fill_sentinel_slots_kernel(int64_t n, const SweepSlot<T>* __restrict__ slots) {
+    const SweepSlot<T> sl = slots[blockIdx.y];
+    if (sl.stop && *sl.stop) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        sl.out[i] = Sentinel<T>::value();
+}
+
+lgp_status sweep_batch(const Factor& F, int nslots, const SweepSlot<double>* slots, bool backward, unsigned* ticket,
+                       hipStream_t s) {
+    if (F.layout == 1) return sweep3_batch(F, nslots, slots, backward, ticket, s);
+    using T = double;
+    const int64_t n = F.n;
+    constexpr int DD = 8, PNW = 4;
+    const size_t pair_shmem = ((size_t)(2 * PNW + F.Hy) * (F.n1 + 2 * F.Hx) + 1) * sizeof(T);
+    const int SLn = (F.nlo + 31) / 32;
+    if (!(F.d == 2 && SLn >= 1 && SLn <= 8 && 32 * SLn <= F.ldl && F.Hy + 4 <= 64 && pair_shmem <= 150 * 1024))
+        return LGP_E_UNSUPPORTED;
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, ticket, 1);
+    hipLaunchKernelGGL(fill_sentinel_slots_kernel<T>, dim3((unsigned)std::min<int64_t>(2048, (n + 255) / 256), nslots),
+                       dim3(256), 0, s, n, slots);
+    const int nbands = (F.n1 + 2 * PNW - 1) / (2 * PNW);
+    auto pick = [&](auto kf) {
+        set_dyn_shmem((const void*)kf, pair_shmem, s);
+        const int grid = persistent_grid((const void*)kf, 64 * PNW, pair_shmem, (int64_t)nbands * nslots);
+        hipLaunchKernelGGL(kf, dim3(grid), dim3(64 * PNW), pair_shmem, s, F.n1, n, F.nlo, F.ldl,
+                           (const int4*)F.d_offs, (const T*)nullptr, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
+                           ticket, (const int*)nullptr, F.Hx, F.Hy, slots, nslots);
+    };
+#define LGP_PAIRB(SLv)                                                                   \
+    case SLv:                                                                            \
+        if (backward) pick(sweep2d_pair_kernel<T, SLv, DD, PNW, true, true>);            \
+        else pick(sweep2d_pair_kernel<T, SLv, DD, PNW, false, false>);                   \
+        break;
+    switch (SLn) {
+        LGP_PAIRB(1) LGP_PAIRB(2) LGP_PAIRB(3) LGP_PAIRB(4) LGP_PAIRB(5) LGP_PAIRB(6) LGP_PAIRB(7) LGP_PAIRB(8)
+    }
+#undef LGP_PAIRB
     LGP_CHECK_LAUNCH();
     return LGP_OK;
 }

@@ -459,6 +459,8 @@ struct S3Args {
     unsigned* prog;
     unsigned* ticket;
     const int* stop;
+    const SweepSlot<T>* slots;   // batched: per-request operator, vectors, progress and flag
+    int nslots;
 };
 
 // out[i'] = in[i'] * scale - sum_k L-term * out[i' + delta_k] in stream
@@ -482,7 +484,8 @@ __global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
     const int r = tid % BXM, grp = tid / BXM;
     const int n1 = a.n1;
     const int64_t n = a.n;
-    if (a.stop && *a.stop) return;
+    if (!a.slots && a.stop && *a.stop) return;
+    const int ns = a.slots ? a.nslots : 1;
     const int4* s_offs = a.offs_in_lds ? s_offs_lds : a.offs;
     if (a.offs_in_lds)
         for (int k = tid; k < a.nother; k += NT) s_offs_lds[k] = a.offs[k];
@@ -490,12 +493,28 @@ __global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
     for (;;) {
         __syncthreads();
         if (tid == 0) {
+            // batched: ticket t is block t / ns (in dependency order) of slot t % ns
             const unsigned tk = atomicAdd(a.ticket, 1u);
-            s_blk = (tk < (unsigned)a.nblk) ? a.blk_order[tk] : -1;
+            s_blk = (tk < (unsigned)(a.nblk * ns)) ? (int)tk : -1;
         }
         __syncthreads();
-        const int blk = s_blk;
-        if (blk < 0) break;
+        const int bt = s_blk;
+        if (bt < 0) break;
+        const int blk = a.blk_order[bt / ns];
+        const T* A = a.A;
+        const T* scale = a.scale;
+        const T* in = a.in;
+        T* out = a.out;
+        unsigned* prog = a.prog;
+        if (a.slots) {
+            const SweepSlot<T> sl = a.slots[bt % ns];
+            if (sl.stop && *sl.stop) continue;   // converged request: skipped (the loop head syncs)
+            A = sl.A;
+            scale = sl.scale;
+            in = sl.in;
+            out = sl.out;
+            prog = sl.prog;
+        }
         const int line = blk / a.nxb;
         const int x0 = (blk - line * a.nxb) * BXM;
         const int iy = line % n1, iz = line / n1;
@@ -503,14 +522,14 @@ __global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
         if (tid == 0) {
             const unsigned needo = (unsigned)min(n1, x0 + BXM + a.Hx);
             if (x0 > 0) {
-                while (ld_coh(&a.prog[line]) < (unsigned)x0) __builtin_amdgcn_s_sleep(1);
+                while (ld_coh(&prog[line]) < (unsigned)x0) __builtin_amdgcn_s_sleep(1);
             }
             if (iy > 0) {
-                while (ld_coh(&a.prog[line - 1]) < needo) __builtin_amdgcn_s_sleep(1);
+                while (ld_coh(&prog[line - 1]) < needo) __builtin_amdgcn_s_sleep(1);
             }
             if (iz > 0) {
                 const int l2 = (iz - 1) * n1 + min(iy + a.Hy, n1 - 1);
-                while (ld_coh(&a.prog[l2]) < needo) __builtin_amdgcn_s_sleep(1);
+                while (ld_coh(&prog[l2]) < needo) __builtin_amdgcn_s_sleep(1);
             }
         }
         __syncthreads();
@@ -537,8 +556,8 @@ __global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
                     okv[u] = ok;
                     const int64_t nb = ok ? mem(ip + o.w) : mip;
                     const int kk = ok ? k : 0;
-                    cv[u] = a.A[(int64_t)kk * a.ldo + (REV ? nb : mip)];
-                    vv[u] = coherent ? ld_coh(&a.out[nb]) : a.out[nb];
+                    cv[u] = A[(int64_t)kk * a.ldo + (REV ? nb : mip)];
+                    vv[u] = coherent ? ld_coh(&out[nb]) : out[nb];
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -546,7 +565,7 @@ __global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
                         const int k = k0 + u * NG;
                         while (okv[u] && Sentinel<T>::is(vv[u])) {
                             const int4 o = s_offs[k];
-                            vv[u] = ld_coh(&a.out[mem(ip + o.w)]);
+                            vv[u] = ld_coh(&out[mem(ip + o.w)]);
                         }
                     }
                     acc += okv[u] ? cv[u] * vv[u] : T(0);
@@ -565,14 +584,14 @@ __global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
             T c = T(0);
             if (k >= 0 && xx < n1 && xx - (m + 1) >= 0) {
                 const int64_t ipr = (int64_t)line * n1 + xx;
-                c = a.A[(int64_t)k * a.ldo + (REV ? mem(ipr - (m + 1)) : mem(ipr))];
+                c = A[(int64_t)k * a.ldo + (REV ? mem(ipr - (m + 1)) : mem(ipr))];
             }
             s_coef[rr][m] = c;
         } else if (tid < BXM * MO + MO) {
             const int m = tid - BXM * MO;       // row x0 - MO + m
             const int xx = x0 - MO + m;
             T v = T(0);
-            if (xx >= 0) v = ld_coh(&a.out[mem((int64_t)line * n1 + xx)]);
+            if (xx >= 0) v = ld_coh(&out[mem((int64_t)line * n1 + xx)]);
             s_prev[m] = v;
         } else if (tid < BXM * MO + MO + BXM) {
             const int rr = tid - BXM * MO - MO;
@@ -580,8 +599,8 @@ __global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
             T v = T(0);
             if (xx < n1) {
                 const int64_t mm = mem((int64_t)line * n1 + xx);
-                v = a.in[mm];
-                if (a.scale) v *= a.scale[mm];
+                v = in[mm];
+                if (scale) v *= scale[mm];
             }
             s_rhs[rr] = v;
         }
@@ -609,11 +628,11 @@ __global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
         }
         __syncthreads();
         if (tid < BXM && x0 + tid < n1) {
-            st_coh(&a.out[mem((int64_t)line * n1 + x0 + tid)], Sentinel<T>::clean(s_prev[tid]));
+            st_coh(&out[mem((int64_t)line * n1 + x0 + tid)], Sentinel<T>::clean(s_prev[tid]));
             wait_own_stores();
         }
         __syncthreads();
-        if (tid == 0) publish(&a.prog[line], (unsigned)min(n1, x0 + BXM));
+        if (tid == 0) publish(&prog[line], (unsigned)min(n1, x0 + BXM));
     }
 }
 
@@ -850,6 +869,8 @@ static lgp_status sweep3_t(Factor& F, bool backward, const T* A, const T* scale,
     a.prog = F.prog;
     a.ticket = F.ticket + 2;
     a.stop = stop;
+    a.slots = nullptr;
+    a.nslots = 0;
     constexpr int NT = 512;
     auto kf = backward ? sweep3d_kernel<T, true, NT> : sweep3d_kernel<T, false, NT>;
     size_t shmem = (size_t)std::max(1, a.nother) * sizeof(int4);
@@ -857,6 +878,63 @@ static lgp_status sweep3_t(Factor& F, bool backward, const T* A, const T* scale,
     if (!a.offs_in_lds) shmem = 16;
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     const int grid = persistent_grid3((const void*)kf, NT, shmem, a.nblk);
+    hipLaunchKernelGGL(kf, dim3(grid), dim3(NT), shmem, s, a);
+    LGP_CHECK_LAUNCH();
+    return LGP_OK;
+}
+
+template <typename T>
+__global__ void fill_sentinel3_slots_kernel(int64_t n, int nlines, const SweepSlot<T>* __restrict__ slots) {
+    const SweepSlot<T> sl = slots[blockIdx.y];
+    if (sl.stop && *sl.stop) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        sl.out[i] = Sentinel<T>::value();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nlines; i += (int64_t)gridDim.x * blockDim.x)
+        sl.prog[i] = 0u;
+}
+
+lgp_status sweep3_batch(const Factor& F, int nslots, const SweepSlot<double>* slots, bool backward, unsigned* ticket,
+                        hipStream_t s) {
+    using T = double;
+    if (!F.A64) return LGP_E_UNSUPPORTED;
+    const int64_t n = F.n;
+    hipLaunchKernelGGL(reset3_kernel, dim3(1), dim3(64), 0, s, ticket, 1);
+    hipLaunchKernelGGL(fill_sentinel3_slots_kernel<T>,
+                       dim3((unsigned)std::min<int64_t>(2048, (n + 255) / 256), nslots), dim3(256), 0, s, n,
+                       F.nlines, slots);
+    int nin = 0;
+    for (int k = 0; k < F.nlo; ++k)
+        if (F.offs[3 * k + 1] == 0 && F.offs[3 * k + 2] == 0) ++nin;
+    S3Args<T> a;
+    a.n1 = F.n1;
+    a.nlo = F.nlo;
+    a.nother = F.nlo - nin;
+    a.Hx = F.Hx;
+    a.Hy = F.Hy;
+    a.BX = F.sBX;
+    a.nxb = F.snxb;
+    a.nblk = F.nlines * F.snxb;
+    a.n = n;
+    a.ldo = F.ldo;
+    a.offs = (const int4*)F.d_offs;
+    a.own = F.own;
+    a.blk_order = F.blk_order;
+    a.A = nullptr;
+    a.scale = nullptr;
+    a.in = nullptr;
+    a.out = nullptr;
+    a.prog = nullptr;
+    a.ticket = ticket;
+    a.stop = nullptr;
+    a.slots = slots;
+    a.nslots = nslots;
+    constexpr int NT = 512;
+    auto kf = backward ? sweep3d_kernel<T, true, NT> : sweep3d_kernel<T, false, NT>;
+    size_t shmem = (size_t)std::max(1, a.nother) * sizeof(int4);
+    a.offs_in_lds = shmem <= 96 * 1024;
+    if (!a.offs_in_lds) shmem = 16;
+    set_dyn_shmem((const void*)kf, shmem, s);
+    const int grid = persistent_grid3((const void*)kf, NT, shmem, (int64_t)a.nblk * nslots);
     hipLaunchKernelGGL(kf, dim3(grid), dim3(NT), shmem, s, a);
     LGP_CHECK_LAUNCH();
     return LGP_OK;

@@ -186,6 +186,27 @@ struct Factor {
     double* fold3 = nullptr;      // folded line coefficients of the 3D path
 };
 
+// One slot of a batched substitution: the operator and vectors of one
+// request (same grid and pattern as the others of the batch). prog: the
+// slot's per-line progress counters (3D kernel), stop: the slot's PCG done flag.
+template <typename T>
+struct SweepSlot {
+    const T* A;
+    const T* scale;
+    const T* in;
+    T* out;
+    unsigned* prog;
+    const int* stop;
+};
+// substitutions of nslots requests in one launch (slots: device table);
+// ticket: one counter; returns LGP_E_UNSUPPORTED where no batched kernel
+// serves the pattern
+lgp_status sweep_batch(const Factor& ref, int nslots, const SweepSlot<double>* slots, bool backward,
+                       unsigned* ticket, hipStream_t s);
+lgp_status sweep3_batch(const Factor& ref, int nslots, const SweepSlot<double>* slots, bool backward,
+                        unsigned* ticket, hipStream_t s);
+int gemm_tuned_variant(GemmMode mode, const GemmArgs& g);
+
 // storage requested for the factor (lgp_dtype values of the ABI)
 enum { STORE_F64 = 0, STORE_F64_F32 = 1, STORE_F32_ONLY = 3 };
 size_t plan_factor(Factor& F, void* buf, int store);
@@ -205,6 +226,14 @@ lgp_status sweep32(Factor& F, bool backward, const float* in, float* out, hipStr
                    const int* stop = nullptr);
 
 // PCG driver
+struct Batch;
+size_t batch_ws_bytes(int64_t n, int nlines, int cap);
+Batch* batch_create(Problem& shape, int cap, void* ws, size_t ws_bytes, hipStream_t s, lgp_status* st);
+void batch_destroy(Batch* B);
+lgp_status batch_add(Batch* B, Problem& P, Factor& M, const double* F, double* x, const lgp_solve_opts& o, int* slot);
+lgp_status batch_step(Batch* B, int iters, int* running);
+lgp_status batch_info(Batch* B, int k, lgp_solve_info* info, int* finished);
+lgp_status batch_remove(Batch* B, int k);
 size_t solve_ws_bytes(int64_t n, bool mixed);
 lgp_status pcg_solve_impl(Problem& P, Factor& M, const double* F, double* x, const lgp_solve_opts& o, void* ws,
                           size_t ws_bytes, hipStream_t s, lgp_solve_info* info);

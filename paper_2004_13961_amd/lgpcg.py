@@ -31,6 +31,8 @@ EXPORTS = [
     "lgp_precond_apply", "lgp_ilu_forward", "lgp_ilu_backward", "lgp_factor_describe",
     "lgp_solve_workspace_bytes", "lgp_pcg_solve", "lgp_factor_const_bytes", "lgp_factor_const",
     "lgp_pcg_solve_noalloc_max_bytes", "lgp_pcg_solve_noalloc", "lgp_ilu_forward_f32", "lgp_ilu_backward_f32",
+    "lgp_batch_workspace_bytes", "lgp_batch_create", "lgp_batch_add", "lgp_batch_step", "lgp_batch_info",
+    "lgp_batch_remove", "lgp_batch_destroy", "lgp_pcg_solve_batched",
 ]
 
 
@@ -95,6 +97,16 @@ def lib():
         "lgp_ilu_forward": (i32, [vp, vp, vp, vp]),
         "lgp_ilu_backward": (i32, [vp, vp, vp, vp]),
         "lgp_ilu_forward_f32": (i32, [vp, vp, vp, vp]),
+        "lgp_batch_workspace_bytes": (sz, [vp, i32]),
+        "lgp_batch_create": (i32, [vp, i32, vp, sz, vp, ctypes.POINTER(vp)]),
+        "lgp_batch_add": (i32, [vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(i32)]),
+        "lgp_batch_step": (i32, [vp, i32, ctypes.POINTER(i32)]),
+        "lgp_batch_info": (i32, [vp, i32, ctypes.POINTER(SolveInfo), ctypes.POINTER(i32)]),
+        "lgp_batch_remove": (i32, [vp, i32]),
+        "lgp_batch_destroy": (None, [vp]),
+        "lgp_pcg_solve_batched": (i32, [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                        ctypes.POINTER(vp), ctypes.POINTER(SolveOpts), vp, sz, vp,
+                                        ctypes.POINTER(SolveInfo)]),
         "lgp_ilu_backward_f32": (i32, [vp, vp, vp, vp]),
         "lgp_factor_describe": (i32, [vp, ctypes.POINTER(FactorDesc)]),
         "lgp_solve_workspace_bytes": (sz, [vp, i32]),

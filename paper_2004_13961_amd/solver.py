@@ -202,3 +202,98 @@ def pcg_solve(problem: Problem, factor: Factor, F: torch.Tensor, x: torch.Tensor
     if st != 0 and raise_on_error:
         raise lgpcg.LgpError(st, "lgp_pcg_solve")
     return x, out
+
+
+class Batch:
+    """Same-shape requests solved together (lgp_batch_*): add() admits a
+    request into a free slot, step(k) runs k PCG iterations of every running
+    request (one launch per kernel for all of them, the iteration replayed
+    as a HIP graph), info() reads a slot's result, remove() frees it. Work
+    runs on the batch's own stream (a graph cannot be captured on the null
+    stream), which waits for the caller's stream at every add."""
+
+    def __init__(self, shape: Problem, slots: int, stream: torch.cuda.Stream = None):
+        L = lib()
+        self.shape = shape
+        self.slots = slots
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        nbytes = L.lgp_batch_workspace_bytes(shape.handle, slots)
+        if nbytes == 0:
+            raise lgpcg.LgpError(1, "lgp_batch_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        check(L.lgp_batch_create(shape.handle, slots, _ptr(self.ws), nbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "lgp_batch_create")
+        self.handle = h
+        self.keep = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and lgpcg._lib is not None:
+            lgpcg._lib.lgp_batch_destroy(h)
+            self.handle = None
+
+    def add(self, problem: Problem, factor: Factor, F: torch.Tensor, x: torch.Tensor = None,
+            rtol: float = 1e-10, max_iter: int = 2000, check: bool = True):
+        _need(F, torch.float64, problem.n, "F")
+        if x is None:
+            x = torch.zeros_like(F)
+        _need(x, torch.float64, problem.n, "x")
+        self.stream.wait_stream(torch.cuda.current_stream())
+        o = lgpcg.SolveOpts(rtol, max_iter, lgpcg.LGP_F64, 0.0, 60, 4)
+        slot = ctypes.c_int(-1)
+        st = lib().lgp_batch_add(self.handle, problem.handle, factor.handle, _ptr(F), _ptr(x), ctypes.byref(o),
+                                 ctypes.byref(slot))
+        if check:
+            lgpcg.check(st, "lgp_batch_add")
+        elif st != 0:
+            return None, x, lgpcg.STATUS.get(st, st)
+        self.keep[slot.value] = (problem, factor, F, x)
+        return slot.value, x, "LGP_OK"
+
+    def step(self, iters: int = 4) -> int:
+        running = ctypes.c_int(0)
+        lgpcg.check(lib().lgp_batch_step(self.handle, iters, ctypes.byref(running)), "lgp_batch_step")
+        return running.value
+
+    def info(self, slot: int):
+        inf = lgpcg.SolveInfo()
+        fin = ctypes.c_int(0)
+        lgpcg.check(lib().lgp_batch_info(self.handle, slot, ctypes.byref(inf), ctypes.byref(fin)), "lgp_batch_info")
+        return dict(iters=inf.iters, outer=inf.outer, relres_true=inf.relres_true,
+                    relres_recursive=inf.relres_recursive, status=lgpcg.STATUS.get(inf.status, inf.status)), bool(fin.value)
+
+    def remove(self, slot: int):
+        lgpcg.check(lib().lgp_batch_remove(self.handle, slot), "lgp_batch_remove")
+        self.keep.pop(slot, None)
+
+
+def pcg_solve_batched(problems, factors, Fs, xs=None, rtol: float = 1e-10, max_iter: int = 2000,
+                      check_every: int = 4, stream: torch.cuda.Stream = None):
+    """lgp_pcg_solve_batched: solve count same-shape requests together.
+    Returns (xs, infos)."""
+    L = lib()
+    count = len(problems)
+    if xs is None:
+        xs = [torch.zeros_like(F) for F in Fs]
+    for P, F, x in zip(problems, Fs, xs):
+        _need(F, torch.float64, P.n, "F")
+        _need(x, torch.float64, P.n, "x")
+    stream = stream if stream is not None else torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    nbytes = L.lgp_batch_workspace_bytes(problems[0].handle, count)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    vp = ctypes.c_void_p
+    arr = lambda vals: (vp * count)(*vals)
+    o = lgpcg.SolveOpts(rtol, max_iter, lgpcg.LGP_F64, 0.0, 60, check_every)
+    infos = (lgpcg.SolveInfo * count)()
+    st = L.lgp_pcg_solve_batched(count, arr([P.handle.value for P in problems]),
+                                 arr([M.handle.value for M in factors]), arr([F.data_ptr() for F in Fs]),
+                                 arr([x.data_ptr() for x in xs]), ctypes.byref(o), _ptr(ws), nbytes,
+                                 vp(stream.cuda_stream), infos)
+    out = [dict(iters=i.iters, outer=i.outer, relres_true=i.relres_true, relres_recursive=i.relres_recursive,
+                status=lgpcg.STATUS.get(i.status, i.status)) for i in infos]
+    if st != 0:
+        raise lgpcg.LgpError(st, "lgp_pcg_solve_batched")
+    torch.cuda.current_stream().wait_stream(stream)
+    return xs, out
