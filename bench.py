@@ -301,6 +301,39 @@ def batched_throughput(count, log):
             "batched_equal_to_alone": bool(same), "iters": [i["iters"] for i in infos]}
 
 
+def serving_run(count, log):
+    """The serving mix (synth.serving_requests: 70 % 2D with N log-uniform in
+    [64, 1024], 30 % 3D with N log-uniform in [32, 192], T in {4, 6, 8},
+    tolerance in {1e-8, 1e-10, 1e-12}), its first `count` requests: once all
+    arriving at time 0 (closed loop, the saturation throughput C), then as a
+    Poisson stream at 0.8 C (seed 4), with an HBM budget of 160 GiB and 8
+    slots per batch. Reports p50 / p99 latency and solves per second."""
+    import torch
+
+    import synth
+    from paper_2004_13961_amd.serving import Server, latency_summary, poisson_arrivals
+    reqs = synth.serving_requests()[:count]
+    budget = 160 << 30
+    recs = Server(budget, slots_per_batch=8, step_iters=2).serve(reqs, [0.0] * count)
+    closed = latency_summary(recs)
+    del recs
+    torch.cuda.empty_cache()
+    rate = 0.8 * closed["solves_per_sec"]
+    recs = Server(budget, slots_per_batch=8, step_iters=2).serve(reqs, list(poisson_arrivals(count, rate)))
+    opened = latency_summary(recs)
+    shapes = len({(r["d"], r["N"], r["T"]) for r in reqs})
+    log("serving %d requests: closed loop %.2f solves/s; Poisson %.2f/s: p50 %.3f s, p99 %.3f s" % (
+        count, closed["solves_per_sec"], rate, opened["p50_s"], opened["p99_s"]))
+    del recs
+    torch.cuda.empty_cache()
+    return {"stream": "first %d of the 4096-request serving mix (%d distinct (d, N, T))" % (count, shapes),
+            "solve": "FP64 PCG, batched per (d, N, pattern)", "budget_bytes": budget,
+            "closed_loop_solves_per_sec": round(closed["solves_per_sec"], 3),
+            "poisson_rate_per_sec": round(rate, 3), "solves_per_sec": round(opened["solves_per_sec"], 3),
+            "p50_latency_s": round(opened["p50_s"], 4), "p99_latency_s": round(opened["p99_s"], 4),
+            "all_ok": bool(closed["all_ok"] and opened["all_ok"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,6 +344,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-lines", type=int, default=64)
     ap.add_argument("--batch", type=int, default=8, help="requests of the batched-throughput section (0: skip)")
+    ap.add_argument("--serve", type=int, default=24, help="requests of the serving section (0: skip)")
     ap.add_argument("--only-extras", action="store_true", help="skip the main workload (batch / serving only)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="finish with one device-to-device copy of this many bytes (a reference "
@@ -332,6 +366,8 @@ def main():
         extras = {}
         if args.batch > 0:
             extras["batched"] = batched_throughput(args.batch, log)
+        if args.serve > 0:
+            extras["serving"] = serving_run(args.serve, log)
         print(json.dumps(extras), flush=True)
         return
 
@@ -512,6 +548,8 @@ def main():
     torch.cuda.empty_cache()
     if args.batch > 0:
         out["batched"] = batched_throughput(args.batch, log)
+    if args.serve > 0:
+        out["serving"] = serving_run(args.serve, log)
     if not args.no_cpu_baseline:
         log("oracle on the host CPU (bounded sample)")
         cb = cpu_baseline(cfg, args.cpu_sample_lines, max(1, it))
