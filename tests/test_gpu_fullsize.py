@@ -300,3 +300,46 @@ def test_fullsize_pcg_mixed_2d(inner):
     assert info["relres_true"] <= C.cfg.tol
     assert res <= 1.5 * C.cfg.tol
     del M32
+
+
+def test_fullsize_3d_N256_mixed():
+    """The largest single-GPU configuration (3D N = 256, T = 6, 16.6 M
+    unknowns) as the benchmark runs it: FP32-only ILU(0) factor, FP32 inner
+    PCG to 1e-4 inside FP64 refinement. Load vector entry by entry against
+    the oracle (1e-12 of each entry's term magnitude), the solution by the
+    oracle's FP64 residual <= 1.5 * tol. The factor itself is checked at
+    N = 128 above; here an FP64 factor would not fit in HBM."""
+    from paper_2004_13961_amd.solver import Factor, Problem, pcg_solve
+    from paper_2004_13961_amd.workload import family_nodal
+    _cases.clear()
+    torch.cuda.empty_cache()
+    cfg = synth.WORKLOADS["3d_N256_T6_mixed"]
+    print("case %s: d=%d N=%d T=%d" % (cfg.name, cfg.d, cfg.N, cfg.T), flush=True)
+    a_g, b_g, f_g, _ = family_nodal(cfg.d, cfg.N, cfg.J, cfg.seed)
+    P = Problem(cfg.d, cfg.N, _dev(a_g), _dev(b_g))
+    F = P.load_vector(_dev(f_g))
+    del a_g, b_g
+    M = Factor(P, cfg.T, store="f32only")
+    torch.cuda.synchronize()
+    desc = M.describe()
+    print("factor kernel %d, %.1f ms" % (desc["factor_kernel"], desc["factor_kernel_ms"]), flush=True)
+    x, info = pcg_solve(P, M, F, rtol=cfg.tol, inner="f32", inner_rtol=1e-4)
+    xg = _host(x)
+    Fg = _host(F)
+    del M, x, F, P
+    torch.cuda.empty_cache()
+    print("solve: outer %d, inner iters %d, solver residual %.2e" % (
+        info["outer"], info["iters"], info["relres_true"]), flush=True)
+    assert info["relres_true"] <= cfg.tol
+
+    B = gk.Basis(cfg.N)
+    c = synth.coefficient_draws(cfg.d, cfg.J, cfg.seed)
+    a_o = owl.coefficient_a(c, B.x)
+    b_o = owl.coefficient_b(cfg.d, B.x)
+    f_o = owl.rhs_f(c, B.x)
+    F_o = gk.load_vector(cfg.d, cfg.N, f_o, B)
+    worst = assert_entrywise(Fg, F_o, 1e-12, load_magnitude(cfg.d, cfg.N, f_o, B), "load vector")
+    print("load vector: worst entry %.2e of its term magnitude" % worst, flush=True)
+    res = np.linalg.norm(F_o - gk.matvec_sumfact(cfg.d, cfg.N, a_o, b_o, xg, B)) / np.linalg.norm(F_o)
+    print("oracle residual %.2e" % res, flush=True)
+    assert res <= 1.5 * cfg.tol
