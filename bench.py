@@ -493,10 +493,15 @@ def main():
         ach = flops / (fac_ms * 1e-3) / 1e12
         fk = {3: "ilu3d_factor_kernel", 2: "ilu_factor2_kernel", 1: "ilu_factor_kernel"}.get(
             desc["factor_kernel"], "ilu_factor_kernel")
+        # a factorisation may take several launches (the 3D kernel: one per
+        # window of z-planes); per launch = per factorisation / launches,
+        # and the event span covers all launches of the factorisation
+        nl = max(1, int(desc.get("factor_launches", 1)))
         roof = dict(kernel=fk + " (ILU(0), Alg. 2, FP64)", bound="alu", achieved=round(ach, 4),
                     peak=FP64_VECTOR_TFLOPS, unit="TFLOP/s", frac=round(ach / FP64_VECTOR_TFLOPS, 6),
-                    flops_per_launch=flops, bytes_written=nnz * (4 if store == "f32only" else 8),
-                    launch_ms=round(fac_ms, 3))
+                    flops_per_factorisation=flops, launches_per_factorisation=nl,
+                    flops_per_launch=flops / nl, launch_ms=round(fac_ms / nl, 3),
+                    factorisation_ms=round(fac_ms, 3), bytes_written=nnz * (4 if store == "f32only" else 8))
     elif dominant == "sweep":
         sk = "sweep3d_kernel" if d == 3 else "sweep2d_pair_kernel"
         roof = dict(kernel=sk + " (forward substitution, Alg. 3, %s)" % sd, bound="hbm",
@@ -544,8 +549,13 @@ def main():
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": roof,
     }
-    del state, P, M, F, x, u32, y32
+    # release the main workload's buffers (the closure above still holds
+    # `state`, and the descriptor holds views of the factor's buffer)
+    state.clear()
+    del P, M, F, x, u32, y32, desc
+    torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    log("main workload released: %.1f GiB still allocated" % (torch.cuda.memory_allocated() / 2**30))
     if args.batch > 0:
         out["batched"] = batched_throughput(args.batch, log)
     if args.serve > 0:

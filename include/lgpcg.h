@@ -220,6 +220,9 @@ typedef struct {
                             L[k*ld + i] = L(i, i + offset_k) with ld >= n; L is NULL
                             when the factor is kept in FP32 only */
     const double* invD;  /* device, n: 1/U(i,i) */
+    int factor_launches; /* launches of the ILU(0) kernel in the last build (the 3D kernel runs
+                            in several, one per window of z-planes); factor_kernel_ms spans
+                            all of them and the small fills between them */
 } lgp_factor_desc;
 lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out);
 

@@ -529,6 +529,7 @@ lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out) {
     out->factor_kernel = F.factor_kernel;
     out->layout = F.layout;
     out->invD = F.invD;
+    out->factor_launches = F.factor_launches;
     return LGP_OK;
 }
 

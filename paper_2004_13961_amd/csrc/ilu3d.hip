@@ -816,6 +816,7 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     F.factor_kernel = 3;
+    F.factor_launches = (int)launches.size();
     LGP_HIP(hipStreamSynchronize(s));
     return LGP_OK;
 }

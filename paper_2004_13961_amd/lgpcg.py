@@ -49,7 +49,8 @@ class FactorDesc(ctypes.Structure):
                 ("offsets", ctypes.POINTER(ctypes.c_int)), ("L", ctypes.c_void_p),
                 ("D", ctypes.c_void_p), ("levels", ctypes.c_int), ("ld", ctypes.c_int),
                 ("factor_kernel_ms", ctypes.c_double), ("factor_kernel", ctypes.c_int),
-                ("layout", ctypes.c_int), ("invD", ctypes.c_void_p)]
+                ("layout", ctypes.c_int), ("invD", ctypes.c_void_p),
+                ("factor_launches", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):

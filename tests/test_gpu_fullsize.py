@@ -287,16 +287,23 @@ def test_fullsize_pcg_fp64(ci):
     assert res <= 1.5 * C.cfg.tol
 
 
-@pytest.mark.parametrize("inner", ["f32", "bf16"])
-def test_fullsize_pcg_mixed_2d(inner):
+@pytest.mark.parametrize("ci,inner", [("2d_N1024_T8", "f32"), ("2d_N1024_T8", "bf16"),
+                                      ("3d_N128_T6", "f32"), ("3d_N128_T6", "bf16")])
+def test_fullsize_pcg_mixed(ci, inner):
+    """FP32 or BF16 inner PCG inside FP64 refinement, with the FP32 copy of
+    the factor (3D: the FP32-only factor the largest configuration uses):
+    the oracle's FP64 residual <= 1.5 * tol; the error against the FP64
+    solution is printed."""
     from paper_2004_13961_amd.solver import Factor, pcg_solve
-    C = _case("2d_N1024_T8")
-    M32 = Factor(C.P, C.cfg.T, store="f32")
+    C = _case(ci)
+    M32 = Factor(C.P, C.cfg.T, store="f32only" if C.d == 3 else "f32")
     x, info = pcg_solve(C.P, M32, C.F, rtol=C.cfg.tol, inner=inner)
     xg = _host(x)
     res = np.linalg.norm(C.F_o - C.matvec_oracle(xg)) / np.linalg.norm(C.F_o)
-    print("2d_N1024_T8 mixed %s: outer %d, inner iters %d, oracle residual %.2e" % (
-        inner, info["outer"], info["iters"], res))
+    x64, _ = pcg_solve(C.P, C.M, C.F, rtol=C.cfg.tol)
+    err = np.linalg.norm(xg - _host(x64)) / np.linalg.norm(_host(x64))
+    print("%s mixed %s: outer %d, inner iters %d, oracle residual %.2e, vs FP64 solution %.2e" % (
+        ci, inner, info["outer"], info["iters"], res, err))
     assert info["relres_true"] <= C.cfg.tol
     assert res <= 1.5 * C.cfg.tol
     del M32
