@@ -223,6 +223,8 @@ typedef struct {
     int factor_launches; /* launches of the ILU(0) kernel in the last build (the 3D kernel runs
                             in several, one per window of z-planes); factor_kernel_ms spans
                             all of them and the small fills between them */
+    int factor_waits;    /* kernel 3: steps of the last build that found a row they read not
+                            yet written and read it again (0 for the other kernels) */
 } lgp_factor_desc;
 lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out);
 

@@ -530,6 +530,7 @@ lgp_status lgp_factor_describe(lgp_factor m, lgp_factor_desc* out) {
     out->layout = F.layout;
     out->invD = F.invD;
     out->factor_launches = F.factor_launches;
+    out->factor_waits = F.factor_waits;
     return LGP_OK;
 }
 

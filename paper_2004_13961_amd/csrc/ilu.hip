@@ -1454,6 +1454,7 @@ lgp_status factor_build(Factor& F, hipStream_t s) {
     const bool timed = hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
     F.factor_kernel_ms = -1.0f;
     F.factor_launches = 1;
+    F.factor_waits = 0;
     lgp_status st = factor_build_impl(F, s, H, timed ? ev : nullptr);
     // drain the stream before H goes away, on success and on failure alike
     if (hipStreamSynchronize(s) != hipSuccess && st == LGP_OK) st = LGP_E_HIP;

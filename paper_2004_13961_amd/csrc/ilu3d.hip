@@ -267,25 +267,27 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
         int jj[PP], lastp[PP];
         int64_t rb[PP];
         int64_t cur = zbase;   // ring row offset of the step being issued
-        // packet descriptors, 64 at a time: lane t of `win` holds packet
-        // w0 + t, `nxt` the next 64 (loaded one window ahead); a descriptor
-        // is read with readlane, so the packet loop waits on no scalar load
-        int4 win, nxt;
+        // Packet descriptors: lane t of `win` holds packet w0 + t and is read
+        // with readlane (no scalar load in the loop); `nxt` collects packets
+        // w0 + 64 .. w0 + 127, one lane per issued packet, from a load made
+        // PP packets earlier (pkn). Every packet issues the same loads (past
+        // the end: a dead packet), so the wait before a use counts exactly
+        // the loads issued after it and never drains the pipeline.
+        const int lastpk = a.npk - 1;
+        int4 win = a.pk[min(lane, lastpk)];
+        int4 nxt = make_int4(0, 0, 0, 0);
+        int4 pkn[PP];
+#pragma unroll
+        for (int b = 0; b < PP; ++b) pkn[b] = a.pk[min(64 + b, lastpk)];
         int w0 = 0;
-        auto load_win = [&](int base) {
-            int4 v = make_int4(0, 0, 0, 0);
-            if (base + lane < a.npk) v = a.pk[base + lane];
-            return v;
-        };
-        win = load_win(0);
-        nxt = load_win(64);
-        auto desc = [&](int p) {
-            if (p >= w0 + 64) {   // wave-uniform: next window
+        auto desc = [&](int b, int p) {
+            if (p >= w0 + 64) {   // wave-uniform: next window (already loaded)
                 w0 += 64;
                 win = nxt;
-                nxt = load_win(w0 + 64);
             }
             const int t = p - w0;
+            if (lane == t) nxt = pkn[b];   // packet p + 64
+            pkn[b] = a.pk[min(p + 64 + PP, lastpk)];
             return make_int4(__builtin_amdgcn_readlane(win.x, t), __builtin_amdgcn_readlane(win.y, t),
                              __builtin_amdgcn_readlane(win.z, t), __builtin_amdgcn_readlane(win.w, t));
         };
@@ -294,15 +296,10 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
         // pair words name (PG packets ahead), so neither stage waits on a
         // load issued in the same iteration.
         auto stage_a = [&](int b, int p) {
-            if (p >= a.npk) {   // wave-uniform: past the end
-#pragma unroll
-                for (int q = 0; q < Q; ++q) pw[b][q] = padw;
-                jj[b] = nlo + 1;
-                lastp[b] = 0;
-                rb[b] = zbase;
-                return;
-            }
-            const int4 P = desc(p);
+            const int4 Pd = desc(b, p);
+            const bool live = p < a.npk;   // wave-uniform
+            const int4 P = live ? Pd : make_int4(0, 0, 0, (int)(nlo + 1));
+            if (!live) cur = zbase;
             if (P.w & (1 << 30)) {   // first packet of a step: its row
                 const int dx = (P.z & 0xFF) - 128, dy = ((P.z >> 8) & 0xFF) - 128, dz = ((P.z >> 16) & 0xFF) - 128;
                 const bool valid = (unsigned)(ix + dx) < (unsigned)n1 && (unsigned)(iy + dy) < (unsigned)n1 &&
@@ -345,13 +342,17 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
             }
         };
         double acc = 0.0;
+        int nslow = 0;
         auto consume = [&](int b) {
 #pragma unroll
             for (int q = 0; q < Q; ++q) acc += *(const double*)(ub + (pw[b][q] & 0xFFFFu)) * g[b][q];
             if (lastp[b]) {   // wave-uniform
                 double tot = wave_total_bcast(acc);
                 acc = 0.0;
-                if (__builtin_expect(isnan(tot), 0)) tot = slow_step(jj[b], rb[b]);
+                if (__builtin_expect(isnan(tot), 0)) {
+                    tot = slow_step(jj[b], rb[b]);
+                    ++nslow;
+                }
                 const double mj = u[jj[b]];
                 if (lane == 0) u[jj[b]] = mj - tot;
             }
@@ -364,11 +365,9 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
         for (int p0 = 0; p0 < a.npk; p0 += PP) {
 #pragma unroll
             for (int b = 0; b < PP; ++b) {
-                if (p0 + b < a.npk) {   // wave-uniform
-                    consume(b);
-                    stage_b((b + PG) % PP);        // packet p0 + b + PG
-                    stage_a(b, p0 + b + PP);
-                }
+                consume(b);                    // packet p0 + b (dead past the end: adds zeros)
+                stage_b((b + PG) % PP);        // packet p0 + b + PG
+                stage_a(b, p0 + b + PP);
             }
         }
 
@@ -405,6 +404,7 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
             if (a.A64) a.A64[(int64_t)k * a.ldo + i] = lk;
             if (a.A32) a.A32[(int64_t)k * a.ldo + i] = (float)lk;
         }
+        if (lane == 0 && nslow) atomicAdd(a.flag + 2, nslow);
         if (lane == 0) {
             st_coh(rowp + nlo, Sentinel<double>::clean(iv));
             a.Dg[i] = Dii;
@@ -794,8 +794,9 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
     a.invD32 = F.invD32;
     a.ticket = F.ticket;
     a.flag = F.flag;
-    constexpr int PP = 4;
-    auto kf = ilu3d_factor_kernel<Q, PP>;
+    auto kf = ilu3d_factor_kernel<Q, 4>;
+    if (const char* e = std::getenv("LGP_F3_PP"))
+        if (std::atoi(e) == 8) kf = ilu3d_factor_kernel<Q, 8>;
     const size_t shmem = (size_t)B * (nlo + 2) * 8;
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (ev) (void)hipEventRecord(ev[0], s);
@@ -817,7 +818,10 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
     if (ev) (void)hipEventRecord(ev[1], s);
     F.factor_kernel = 3;
     F.factor_launches = (int)launches.size();
+    int fl[4] = {0, 0, 0, 0};
+    LGP_HIP(hipMemcpyAsync(fl, F.flag, 16, hipMemcpyDeviceToHost, s));
     LGP_HIP(hipStreamSynchronize(s));
+    F.factor_waits = fl[2];
     return LGP_OK;
 }
 

@@ -150,6 +150,7 @@ struct Factor {
     float factor_kernel_ms;   // duration of the ILU(0) kernel of the last build (HIP events)
     int factor_kernel;        // 2: dataflow kernel, 1: generic kernel
     int factor_launches;      // launches of that kernel in the last build
+    int factor_waits = 0;     // 3D chunked kernel: steps that found a row they read not yet written
     // kind 1: the constant-coefficient operator solved exactly (matrix
     // diagonalisation); only P, d, n1, n and the cc* fields are used
     int kind = 0;

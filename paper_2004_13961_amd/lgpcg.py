@@ -50,7 +50,7 @@ class FactorDesc(ctypes.Structure):
                 ("D", ctypes.c_void_p), ("levels", ctypes.c_int), ("ld", ctypes.c_int),
                 ("factor_kernel_ms", ctypes.c_double), ("factor_kernel", ctypes.c_int),
                 ("layout", ctypes.c_int), ("invD", ctypes.c_void_p),
-                ("factor_launches", ctypes.c_int)]
+                ("factor_launches", ctypes.c_int), ("factor_waits", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):

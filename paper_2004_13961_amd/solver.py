@@ -178,7 +178,7 @@ class Factor:
         return dict(offsets=offs, n_lower=nlo, ld=ld, L=Lv, invD=iv, D=Dv,
                     levels=dsc.levels, n=n, factor_kernel_ms=dsc.factor_kernel_ms,
                     factor_kernel=dsc.factor_kernel, layout=dsc.layout,
-                    factor_launches=dsc.factor_launches)
+                    factor_launches=dsc.factor_launches, factor_waits=dsc.factor_waits)
 
 
 def pcg_solve(problem: Problem, factor: Factor, F: torch.Tensor, x: torch.Tensor = None, rtol: float = 1e-10,
