@@ -194,6 +194,67 @@ def cpu_baseline(cfg, sample_lines, iters):
     return dict(total=total, sample=sample, threads=threads)
 
 
+def cpu_full(cfg, log):
+    """The oracle on the whole workload, end to end, nothing sampled or
+    scaled: coefficients, load vector, truncated series and pattern, the
+    stencil rows of M for every row, Alg. 2 on every row, then PCG (Alg. 1)
+    with the oracle's sum-factorised product and its Alg. 3/4 to the
+    workload's tolerance; the residual checked by the oracle's product."""
+    import platform
+
+    import synth
+    from oracle import galerkin as gk
+    from oracle import ilu as oilu
+    from oracle import pcg as opcg
+    from oracle import precond as pc
+    from oracle import workload as owl
+    d, N, n1 = cfg.d, cfg.N, cfg.N - 1
+    tt = {}
+    t0 = time.perf_counter()
+    B = gk.Basis(N)
+    c = synth.coefficient_draws(d, cfg.J, cfg.seed)
+    a = owl.coefficient_a(c, B.x)
+    b = owl.coefficient_b(d, B.x)
+    F = gk.load_vector(d, N, owl.rhs_f(c, B.x), B)
+    ah, bh = pc.series_pair(a, b, B, cfg.T, cfg.T)
+    offs = pc.stencil_offsets(ah, bh)
+    tt["setup_s"] = time.perf_counter() - t0
+    log("cpu full: setup %.1f s" % tt["setup_s"])
+    t1 = time.perf_counter()
+    H = pc.stencil_rows(d, n1, ah, bh, offs)
+    tt["stencil_rows_s"] = time.perf_counter() - t1
+    log("cpu full: stencil rows %.1f s" % tt["stencil_rows_s"])
+    t1 = time.perf_counter()
+    st = oilu.StencilILU(d, n1, offs, H).factor()
+    tt["ilu0_s"] = time.perf_counter() - t1
+    log("cpu full: ILU(0) %.1f s" % tt["ilu0_s"])
+    mv = lambda v: gk.matvec_sumfact(d, N, a, b, v, B)
+    t1 = time.perf_counter()
+    x, iters, hist = opcg.pcg(mv, st.apply, F, cfg.tol)
+    tt["pcg_s"] = time.perf_counter() - t1
+    total = time.perf_counter() - t0
+    relres = float(np.linalg.norm(F - mv(x)) / np.linalg.norm(F))
+    log("cpu full: PCG %d iterations %.1f s, residual %.2e" % (iters, tt["pcg_s"], relres))
+    model = platform.processor()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"workload": cfg.name, "kind": "oracle", "mode": "full run, nothing sampled",
+            "seconds": round(total, 2), "requests_per_sec": 1.0 / total,
+            "phases_s": {k: round(v, 2) for k, v in tt.items()}, "pcg_iterations": iters,
+            "relres_oracle": relres, "cpu_model": model, "cores_available": cores,
+            "threads": {"oracle C loops": 1,
+                        "numpy BLAS": os.environ.get("OMP_NUM_THREADS", "library default")}}
+
+
 def lower_entries_prefix(d, n1, offsets, lines):
     """In-grid lower entries of L in the rows of the first `lines` grid lines
     (z = 0 plane in 3D)."""
@@ -346,6 +407,8 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="requests of the batched-throughput section (0: skip)")
     ap.add_argument("--serve", type=int, default=24, help="requests of the serving section (0: skip)")
     ap.add_argument("--only-extras", action="store_true", help="skip the main workload (batch / serving only)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="run the oracle on the whole workload on the host CPU (no GPU) and print its timing")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="finish with one device-to-device copy of this many bytes (a reference "
                          "for hardware byte counters)")
@@ -354,6 +417,11 @@ def main():
         print("bench.py measures one GPU only: the solver runs each request on a single GPU "
               "and has no multi-GPU path (requested --gpus %d)" % args.gpus)
         sys.exit(2)
+
+    if args.cpu_full:
+        import synth
+        print(json.dumps(cpu_full(synth.WORKLOADS[args.workload], log)), flush=True)
+        return
 
     import torch
 

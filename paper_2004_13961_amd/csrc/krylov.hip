@@ -21,7 +21,7 @@ constexpr int VBS = 256;
 
 enum {
     SC_RHO = 0, SC_RHO_OLD, SC_PW, SC_RR, SC_ALPHA, SC_BETA, SC_FF, SC_THRESH2,
-    SC_K, SC_KMAX, SC_COUNT = 16
+    SC_K, SC_KMAX, SC_RHO2, SC_COUNT = 16
 };
 enum { FL_DONE = 0, FL_BREAK = 1, FL_FIRST = 2, FL_XZERO = 3, FL_COUNT = 4 };
 
@@ -48,7 +48,7 @@ static size_t plan_ws(SolveWS& S, int64_t n, bool mixed, void* buf) {
     } else {
         S.r32 = S.z32 = S.p32 = S.w32 = S.e32 = S.y32 = nullptr;
     }
-    S.part = c.take<double>(NPART);
+    S.part = c.take<double>(2 * NPART);   // two sets: p.w, then r.r in the same kernel
     S.sc = c.take<double>(SC_COUNT);
     S.fl = c.take<int>(FL_COUNT);
     S.bytes = c.off + 256;
@@ -167,6 +167,78 @@ __global__ __launch_bounds__(VBS) void update_xr_kernel(int64_t n, T* __restrict
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// The single solve's iteration fuses the final sums into the vector updates:
+// every workgroup adds the same partials in the same order, so all of them
+// hold the same scalar, and workgroup 0 records it. rho alternates between
+// two slots by the parity of k, so the workgroups that read rho_old never
+// race the one that writes rho. The arithmetic is the one of the separate
+// kernels above (which the batched iteration keeps), value for value.
+__device__ inline int rho_slot(const double* sc, bool current) {
+    const bool odd = ((long long)sc[SC_K] & 1) != 0;
+    return (odd == current) ? SC_RHO2 : SC_RHO;
+}
+
+// rho = r.z (from the partials); beta = rho / rho_old (0 on the first
+// iteration); p = z + beta p
+template <typename T>
+__global__ __launch_bounds__(VBS) void rho_update_p_kernel(int64_t n, const T* __restrict__ z, T* __restrict__ p,
+                                                           const double* __restrict__ part, double* __restrict__ sc,
+                                                           int* __restrict__ fl) {
+    if (fl[FL_DONE]) return;
+    const double rho = sum_parts(part);
+    __shared__ double s_rho;
+    if (threadIdx.x == 0) s_rho = rho;
+    __syncthreads();
+    const double r0 = s_rho;
+    const bool first = fl[FL_FIRST] != 0;
+    const double rho_old = sc[rho_slot(sc, false)];
+    const double beta = first ? 0.0 : r0 / rho_old;
+    const bool bad = !(r0 > 0.0) || !isfinite(r0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[rho_slot(sc, true)] = r0;
+        sc[SC_RHO_OLD] = rho_old;
+        sc[SC_BETA] = beta;
+        if (bad) { fl[FL_BREAK] = 1; fl[FL_DONE] = 1; }
+    }
+    if (bad) return;
+    const T b = (T)beta;
+    for (int64_t i = blockIdx.x * (int64_t)VBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * VBS)
+        p[i] = first ? z[i] : z[i] + b * p[i];
+}
+
+// alpha = rho / p.w (from the partials); x += alpha p; r -= alpha w; partials of r.r
+template <typename T>
+__global__ __launch_bounds__(VBS) void alpha_update_xr_kernel(int64_t n, T* __restrict__ x, T* __restrict__ r,
+                                                              const T* __restrict__ p, const T* __restrict__ w,
+                                                              const double* __restrict__ part_pw,
+                                                              double* __restrict__ part_rr, double* __restrict__ sc,
+                                                              int* __restrict__ fl) {
+    if (fl[FL_DONE]) return;
+    const double pw = sum_parts(part_pw);
+    __shared__ double s_pw;
+    if (threadIdx.x == 0) s_pw = pw;
+    __syncthreads();
+    const double pw0 = s_pw;
+    const double al = sc[rho_slot(sc, true)] / pw0;
+    const bool bad = !(pw0 > 0.0) || !isfinite(pw0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[SC_PW] = pw0;
+        sc[SC_ALPHA] = al;
+        if (bad) { fl[FL_BREAK] = 1; fl[FL_DONE] = 1; }
+    }
+    if (bad) return;
+    const T alpha = (T)al;
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VBS + threadIdx.x; i < n; i += (int64_t)NPART * VBS) {
+        x[i] += alpha * p[i];
+        const T ri = r[i] - alpha * w[i];
+        r[i] = ri;
+        s += (double)ri * (double)ri;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+
 // r = F - w
 // r = F - w, or r = F when x was all zeros (then the product was skipped and
 // w holds nothing)
@@ -254,18 +326,20 @@ static lgp_status pcg_loop(int64_t n, T* x, T* r, T* z, T* p, T* w, SolveWS& S, 
     for (;;) {
         for (int it = 0; it < check_every; ++it) {
             if ((st = pc(r, z)) != LGP_OK) return st;
+            // Alg. 1: rho = r.z, beta, p = z + beta p | w = K p | alpha = rho / p.w,
+            // x += alpha p, r -= alpha w | ||r||, k += 1, stop test: five
+            // vector kernels besides the product and the substitutions
             hipLaunchKernelGGL(dot_kernel<T>, dim3(NPART), dim3(VBS), 0, s, n, (const T*)r, (const T*)z, S.part,
                                (const int*)S.fl);
-            hipLaunchKernelGGL(fin_rho_kernel, dim3(1), dim3(VBS), 0, s, (const double*)S.part, S.sc, S.fl);
-            hipLaunchKernelGGL(update_p_kernel<T>, dim3(vgrid(n)), dim3(VBS), 0, s, n, (const T*)z, p,
-                               (const double*)S.sc, (const int*)S.fl);
+            hipLaunchKernelGGL(rho_update_p_kernel<T>, dim3(vgrid(n)), dim3(VBS), 0, s, n, (const T*)z, p,
+                               (const double*)S.part, S.sc, S.fl);
             if ((st = mv(p, w)) != LGP_OK) return st;   // kernels return early once done
             hipLaunchKernelGGL(dot_kernel<T>, dim3(NPART), dim3(VBS), 0, s, n, (const T*)p, (const T*)w, S.part,
                                (const int*)S.fl);
-            hipLaunchKernelGGL(fin_alpha_kernel, dim3(1), dim3(VBS), 0, s, (const double*)S.part, S.sc, S.fl);
-            hipLaunchKernelGGL(update_xr_kernel<T>, dim3(NPART), dim3(VBS), 0, s, n, x, r, (const T*)p, (const T*)w,
-                               (const double*)S.sc, S.part, (const int*)S.fl);
-            hipLaunchKernelGGL(fin_rr_kernel, dim3(1), dim3(VBS), 0, s, (const double*)S.part, S.sc, S.fl, 1);
+            hipLaunchKernelGGL(alpha_update_xr_kernel<T>, dim3(NPART), dim3(VBS), 0, s, n, x, r, (const T*)p,
+                               (const T*)w, (const double*)S.part, S.part + NPART, S.sc, S.fl);
+            hipLaunchKernelGGL(fin_rr_kernel, dim3(1), dim3(VBS), 0, s, (const double*)(S.part + NPART), S.sc, S.fl,
+                               1);
             LGP_CHECK_LAUNCH();
         }
         if ((st = read_state(S, s, h)) != LGP_OK) return st;
