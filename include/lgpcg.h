@@ -309,6 +309,35 @@ lgp_status lgp_pcg_solve_batched(int count, const lgp_problem* p, const lgp_fact
                                  double* const* x, const lgp_solve_opts* opts, void* ws, size_t ws_bytes,
                                  void* stream, lgp_solve_info* info);
 
+/* ------------------------------------------- fast Legendre transforms -- */
+/* The discrete Legendre transforms of Sec. 2.2 at a problem's N+1
+ * Legendre-Gauss nodes, computed in O(N (log N)^2) (the approach of Hale and
+ * Townsend that the paper cites: an asymptotic expansion of L_n summed with
+ * FFTs where it is accurate to 1e-16, the three-term recurrence elsewhere),
+ * and the product of Sec. 4.3 through them (steps 1-4: phi to Legendre
+ * coefficients, BDLT, pointwise coefficients, FDLT, recombination onto the
+ * test functions). The product equals lgp_matvec in FP64 up to rounding;
+ * lgp_matvec keeps the dense per-direction contractions on the matrix
+ * cores, which are faster at every N this library serves. Served for
+ * N + 1 <= 2048 (LGP_E_UNSUPPORTED above). The handle keeps a pointer to
+ * the problem, which must outlive it; its buffer (caller-owned device
+ * memory of lgp_dlt_bytes bytes) holds the plan and all scratch, so
+ * transforms and products on one handle must be stream-ordered. */
+typedef struct lgp_dlt_s* lgp_dlt;
+size_t lgp_dlt_bytes(lgp_problem p);
+/* Plan on the host, tables uploaded on `stream` (synchronised). */
+lgp_status lgp_dlt_create(lgp_problem p, void* buf, size_t buf_bytes, void* stream, lgp_dlt* out);
+/* count (1 .. max((N+1)^(d-1), 16)) contiguous vectors of N+1 doubles, in to out
+ * (device). forward = 0: BDLT, f_k = sum_n c_n L_n(x_k); forward = 1: FDLT,
+ * c_n = (2n+1)/2 sum_k w_k f_k L_n(x_k). */
+lgp_status lgp_dlt_lines(lgp_dlt h, int forward, int64_t count, const double* in, double* out, void* stream);
+/* y = (A + B) u in FP64 through the fast transforms; u, y device (N-1)^d
+ * doubles, must not alias. */
+lgp_status lgp_matvec_fast(lgp_dlt h, const double* u, double* y, void* stream);
+/* Number of degree blocks summed by the expansion (0: every degree direct). */
+int lgp_dlt_blocks(lgp_dlt h);
+void lgp_dlt_destroy(lgp_dlt h);
+
 /* ------------------------------------------------ allocation-free solve -- */
 /* For callers that cannot allocate device memory at solve time (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):

@@ -713,4 +713,50 @@ lgp_status lgp_pcg_solve_noalloc(lgp_problem p, lgp_factor m, const double* F, d
     return lgp_pcg_solve(p, m, F, x, opts, ws, (size_t)LGP_NOALLOC_SCRATCH_BYTES, stream, info);
 }
 
+// ------------------------------------------------- fast transforms -------
+struct lgp_dlt_s {
+    lgp::Dlt* D;
+};
+
+size_t lgp_dlt_bytes(lgp_problem p) {
+    if (!p || !lgp::dlt_supported(p->P)) return 0;
+    return lgp::dlt_bytes(p->P);
+}
+
+lgp_status lgp_dlt_create(lgp_problem p, void* buf, size_t buf_bytes, void* stream, lgp_dlt* out) {
+    if (!p || !buf || !out) return LGP_E_ARG;
+    if (!lgp::dlt_supported(p->P)) return LGP_E_UNSUPPORTED;
+    LGP_ONE_THREAD();
+    lgp_dlt_s* h = new (std::nothrow) lgp_dlt_s();
+    if (!h) return LGP_E_NOMEM;
+    lgp_status st = LGP_OK;
+    h->D = lgp::dlt_create(p->P, buf, buf_bytes, (hipStream_t)stream, &st);
+    if (!h->D) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return LGP_OK;
+}
+
+lgp_status lgp_dlt_lines(lgp_dlt h, int forward, int64_t count, const double* in, double* out, void* stream) {
+    if (!h || !in || !out) return LGP_E_ARG;
+    LGP_ONE_THREAD();
+    return lgp::dlt_apply(*h->D, forward != 0, count, in, out, (hipStream_t)stream);
+}
+
+lgp_status lgp_matvec_fast(lgp_dlt h, const double* u, double* y, void* stream) {
+    if (!h || !u || !y || u == y) return LGP_E_ARG;
+    LGP_ONE_THREAD();
+    return lgp::matvec_fast(*h->D, u, y, (hipStream_t)stream);
+}
+
+int lgp_dlt_blocks(lgp_dlt h) { return h ? lgp::dlt_blocks(*h->D) : 0; }
+
+void lgp_dlt_destroy(lgp_dlt h) {
+    if (!h) return;
+    lgp::dlt_destroy(h->D);
+    delete h;
+}
+
 }  // extern "C"

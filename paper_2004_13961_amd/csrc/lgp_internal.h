@@ -109,6 +109,16 @@ lgp_status matvec_f64(Problem& P, const double* u, double* y, hipStream_t s, con
 lgp_status matvec_lp(Problem& P, const float* u, float* y, GemmMode mode, hipStream_t s, const int* stop = nullptr);
 lgp_status load_vector(Problem& P, const double* f, double* F, hipStream_t s);
 
+// ------------------------------------------------- fast transforms -------
+struct Dlt;
+bool dlt_supported(const Problem& P);
+size_t dlt_bytes(Problem& P);
+Dlt* dlt_create(Problem& P, void* buf, size_t bytes, hipStream_t s, lgp_status* st);
+void dlt_destroy(Dlt* D);
+lgp_status dlt_apply(Dlt& D, bool forward, int64_t count, const double* in, double* out, hipStream_t s);
+lgp_status matvec_fast(Dlt& D, const double* u, double* y, hipStream_t s);
+int dlt_blocks(const Dlt& D);
+
 // ------------------------------------------------------------ factor -----
 struct Factor {
     Problem* P;

@@ -33,6 +33,7 @@ EXPORTS = [
     "lgp_pcg_solve_noalloc_max_bytes", "lgp_pcg_solve_noalloc", "lgp_ilu_forward_f32", "lgp_ilu_backward_f32",
     "lgp_batch_workspace_bytes", "lgp_batch_create", "lgp_batch_add", "lgp_batch_step", "lgp_batch_info",
     "lgp_batch_remove", "lgp_batch_destroy", "lgp_pcg_solve_batched",
+    "lgp_dlt_bytes", "lgp_dlt_create", "lgp_dlt_lines", "lgp_matvec_fast", "lgp_dlt_blocks", "lgp_dlt_destroy",
 ]
 
 
@@ -114,6 +115,12 @@ def lib():
         "lgp_pcg_solve": (i32, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts), vp, sz, vp,
                                 ctypes.POINTER(SolveInfo)]),
         "lgp_pcg_solve_noalloc_max_bytes": (sz, []),
+        "lgp_dlt_bytes": (sz, [vp]),
+        "lgp_dlt_create": (i32, [vp, vp, sz, vp, ctypes.POINTER(vp)]),
+        "lgp_dlt_lines": (i32, [vp, i32, i64, vp, vp, vp]),
+        "lgp_matvec_fast": (i32, [vp, vp, vp, vp]),
+        "lgp_dlt_blocks": (i32, [vp]),
+        "lgp_dlt_destroy": (None, [vp]),
         "lgp_pcg_solve_noalloc": (i32, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)]),
     }
     for name, (res, args) in sig.items():

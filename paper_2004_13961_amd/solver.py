@@ -298,3 +298,48 @@ def pcg_solve_batched(problems, factors, Fs, xs=None, rtol: float = 1e-10, max_i
         raise lgpcg.LgpError(st, "lgp_pcg_solve_batched")
     torch.cuda.current_stream().wait_stream(stream)
     return xs, out
+
+
+class FastTransforms:
+    """Fast discrete Legendre transforms at a problem's nodes and the product
+    of Sec. 4.3 through them (lgp_dlt_*). The problem must outlive it."""
+
+    def __init__(self, problem: Problem):
+        L = lib()
+        self.problem = problem
+        nbytes = L.lgp_dlt_bytes(problem.handle)
+        if nbytes == 0:
+            raise lgpcg.LgpError(8, "lgp_dlt_bytes")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        check(L.lgp_dlt_create(problem.handle, _ptr(self.buf), nbytes, _stream(), ctypes.byref(h)), "lgp_dlt_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and lgpcg._lib is not None:
+            lgpcg._lib.lgp_dlt_destroy(h)
+            self.handle = None
+
+    def blocks(self) -> int:
+        return lib().lgp_dlt_blocks(self.handle)
+
+    def lines(self, v: torch.Tensor, forward: bool = False, out: torch.Tensor = None) -> torch.Tensor:
+        """BDLT (forward=False) or FDLT of each row of v (count x (N+1))."""
+        q = self.problem.q
+        count = v.numel() // q
+        _need(v, torch.float64, count * q, "v")
+        if out is None:
+            out = torch.empty_like(v)
+        _need(out, torch.float64, count * q, "out")
+        check(lib().lgp_dlt_lines(self.handle, 1 if forward else 0, count, _ptr(v), _ptr(out), _stream()),
+              "lgp_dlt_lines")
+        return out
+
+    def matvec(self, u: torch.Tensor, y: torch.Tensor = None) -> torch.Tensor:
+        n = self.problem.n
+        _need(u, torch.float64, n, "u")
+        if y is None:
+            y = torch.empty_like(u)
+        check(lib().lgp_matvec_fast(self.handle, _ptr(u), _ptr(y), _stream()), "lgp_matvec_fast")
+        return y
