@@ -194,6 +194,52 @@ def cpu_baseline(cfg, sample_lines, iters):
     return dict(total=total, sample=sample, threads=threads)
 
 
+def fast_dlt_section(log):
+    """The product of Sec. 4.3 through the fast discrete Legendre transforms
+    (lgp_matvec_fast) against the dense contractions on the matrix cores
+    (lgp_matvec), at 2D N = 1024 (config 1's grid), and one batch of 1D
+    transforms (all 1025 lines of the grid) each way. Events on the stream
+    the library runs on."""
+    import torch
+
+    import synth
+    from paper_2004_13961_amd.solver import FastTransforms, Problem
+    from paper_2004_13961_amd.workload import family_nodal
+    cfg = synth.WORKLOADS["2d_N1024_T8"]
+    d, N = cfg.d, cfg.N
+    a, b, _, _ = family_nodal(d, N, cfg.J, cfg.seed, with_rhs=False)
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v).reshape(-1)).cuda()
+    P = Problem(d, N, dev(a), dev(b))
+    T = FastTransforms(P)
+    u = torch.rand(P.n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(u)
+    yd = torch.empty_like(u)
+    c = torch.rand(P.nq, dtype=torch.float64, device="cuda")
+    f = torch.empty_like(c)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    fast = timed(lambda: T.matvec(u, y), 3)
+    dense = timed(lambda: P.matvec(u, yd), 10)
+    bwd = timed(lambda: T.lines(c, forward=False, out=f), 3)
+    fwd = timed(lambda: T.lines(c, forward=True, out=f), 3)
+    diff = float(torch.max(torch.abs(y - yd)) / torch.max(torch.abs(yd)))
+    log("fast DLT (2D N=1024): product %.2f ms (dense %.3f ms), 1025 BDLTs %.2f ms, FDLTs %.2f ms, %d blocks" % (
+        fast, dense, bwd, fwd, T.blocks()))
+    return {"workload": "2d_N1024_T8", "fast_product_ms": round(fast, 3), "dense_product_ms": round(dense, 4),
+            "bdlt_1025_lines_ms": round(bwd, 3), "fdlt_1025_lines_ms": round(fwd, 3), "expansion_blocks": T.blocks(),
+            "max_rel_diff_fast_vs_dense": diff}
+
+
 def cpu_full(cfg, log):
     """The oracle on the whole workload, end to end, nothing sampled or
     scaled: coefficients, load vector, truncated series and pattern, the
@@ -407,6 +453,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="requests of the batched-throughput section (0: skip)")
     ap.add_argument("--serve", type=int, default=24, help="requests of the serving section (0: skip)")
     ap.add_argument("--only-extras", action="store_true", help="skip the main workload (batch / serving only)")
+    ap.add_argument("--no-fast-dlt", action="store_true", help="skip the fast-transform product section")
     ap.add_argument("--cpu-full", action="store_true",
                     help="run the oracle on the whole workload on the host CPU (no GPU) and print its timing")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -436,6 +483,8 @@ def main():
             extras["batched"] = batched_throughput(args.batch, log)
         if args.serve > 0:
             extras["serving"] = serving_run(args.serve, log)
+        if not args.no_fast_dlt:
+            extras["fast_dlt"] = fast_dlt_section(log)
         print(json.dumps(extras), flush=True)
         return
 
@@ -628,6 +677,8 @@ def main():
         out["batched"] = batched_throughput(args.batch, log)
     if args.serve > 0:
         out["serving"] = serving_run(args.serve, log)
+    if not args.no_fast_dlt:
+        out["fast_dlt"] = fast_dlt_section(log)
     if not args.no_cpu_baseline:
         log("oracle on the host CPU (bounded sample)")
         cb = cpu_baseline(cfg, args.cpu_sample_lines, max(1, it))
