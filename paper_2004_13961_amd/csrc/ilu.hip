@@ -1467,7 +1467,8 @@ lgp_status factor_build(Factor& F, hipStream_t s) {
     return st;
 }
 
-lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hipEvent_t* ev);
+lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, const std::vector<unsigned>& pw,
+                       hipEvent_t* ev);
 lgp_status factor3_generic_finish(Factor& F, hipStream_t s);
 
 // d = 3: folded coefficients, then the chunked kernel (offset-major output
@@ -1481,7 +1482,7 @@ static lgp_status factor_build3_impl(Factor& F, hipStream_t s, FactorHostTables&
     hipLaunchKernelGGL(fold_kernel, dim3(std::min(F.nlines, 4096)), dim3(256), 0, s, d, n1, T, h,
                        (const double*)F.band, (const double*)F.coefA, (const double*)F.coefB, F.fold3, F.nlines);
     LGP_CHECK_LAUNCH();
-    if (F.fB > 0) return factor3_run(F, s, H.st4, ev);
+    if (F.fB > 0) return factor3_run(F, s, H.st4, H.pw, ev);
     // generic kernel: rows in level order, done flags in y_tmp, rows of L in
     // the window (which holds the whole grid here)
     F.factor_kernel = 1;

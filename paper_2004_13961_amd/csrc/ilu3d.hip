@@ -22,17 +22,24 @@
 // earlier rows of its own chunk. Consecutive rows of a chunk read largely
 // the same rows of L at nearly the same time, from the same L2.
 //
-// Ring. The ring slot of a row is (rank of its chunk * B + ix mod B) mod R.
-// A launch covers chunks of keys [k0, k1) and reads rows of keys down to
-// k0 - reach (reach = e + wy Hy + wz Hz): the launches are cut so that all of
-// those rows fit in R slots, so no slot in use is overwritten; the slots a
-// launch writes are filled with the sentinel before it.
+// Window. The window holds Z whole z-planes of rows, row (ix, iy, iz) in
+// slot ((iz mod Z) n1 + iy) n1 + ix. A launch covers chunks of keys [k0, k1)
+// and reads rows of keys down to k0 - reach (reach = e + wy Hy + wz Hz): the
+// launches are cut so that all of those rows span at most Z planes, so no
+// slot in use is overwritten; the slots a launch writes are filled with the
+// sentinel before it. A window row holds L(r, r + delta) at delta's position
+// p(delta) = P0 + dz XY + dy X + dx in the lower half of the stencil's
+// bounding box (X = 2 Hx + 1, XY = X (2 Hy + 1), P0 = p(0); zero at holes,
+// columns outside the grid and up to slot PD), and 1/D(r) at slot PD.
 //
 // Each row is computed left-looking (reading R1): u_j = M(i, i+d_j) -
 // sum over pairs (k, l) with d_k = d_j + d_l of u_k L(i+d_j, i+d_k), the
 // offsets j taken in the host's dataflow order; then L(i, i+d_j) = u_j /
-// D(i+d_j), D(i) = M(i,i) - sum_j u_j L(i, i+d_j). The pairs of all steps
-// form one list cut into packets of at most 64 (one per lane); the loads of
+// D(i+d_j), D(i) = M(i,i) - sum_j u_j L(i, i+d_j). The row's u vector sits in
+// LDS at the same box positions, so p(d_k) = p(d_l) + p(d_j) - P0 and a pair
+// is the single byte offset 8 p(d_l): two pairs per 32-bit word. The pairs
+// of all steps form one list (each step padded to 128 pairs with P0, whose
+// window slot is zero) cut into packets of 512 (8 per lane); the loads of
 // the next PP packets are in flight while a packet is consumed. A row's
 // entries are published together when it is done; a gathered sentinel sends
 // the step to coherent re-reads.
@@ -73,12 +80,20 @@ static ChunkKeys chunk_keys(int B, int Hx, int Hy, int Hz) {
 // pairs per lane in one packet of the 3D factor kernel
 constexpr int kPairsPerLane = 8;
 
-static int factor3_waves(int nlo) {
-    const size_t per = (size_t)(nlo + 2) * 8;
+// The chunked kernel lays out each row's u vector (LDS) and the rows of the
+// window by position in the lower half of the stencil's bounding box,
+// p(delta) = P0 + dz XY + dy X + dx (X = 2 Hx + 1, XY = X (2 Hy + 1), P0 the
+// diagonal), so a pair of the recurrence is one 16-bit byte offset: the
+// neighbour row's entry p(delta_l) and u at p(delta_l) + (p(delta_j) - P0).
+// This needs the box order (z, y, x) to be the order of the columns, i.e. a
+// grid wider than twice the reach in x and y; other grids take the generic
+// kernel. Returns the rows per chunk (0: generic kernel).
+static int factor3_waves(const Factor& F) {
+    if (F.n1 <= 2 * std::max(F.Hx, F.Hy) || F.bPD + 1 > 8191) return 0;
+    const size_t per = (size_t)(F.bP0 + 2) * 8;
     const int fit = (int)((150u * 1024u) / per);
     int B = 8;   // a power of two (slot arithmetic by shifts)
     while (B > fit) B >>= 1;
-    if (nlo + 2 > 8191) B = 0;   // pair words carry byte offsets in 16 bits
     return B;
 }
 
@@ -107,11 +122,17 @@ size_t plan_factor3(Factor& F, void* buf, int store) {
     F.ldo = (n + 63) & ~(int64_t)63;
     F.has64 = (store != STORE_F32_ONLY);
     F.has32 = (store != STORE_F64);
-    F.fB = factor3_waves(nlo);
+    F.bX = 2 * F.Hx + 1;
+    F.bXY = F.bX * (2 * F.Hy + 1);
+    F.bP0 = F.Hz * F.bXY + F.Hy * F.bX + F.Hx;
+    F.bPD = F.Hz * F.bXY + (F.Hy + 1) * F.bX;
+    F.ldr = ((F.bPD + 1) + 15) & ~15;
+    F.fB = factor3_waves(F);
     F.nxb = F.fB > 0 ? (n1 + F.fB - 1) / F.fB : 0;
     F.nchunks = F.nxb * F.nlines;
     // the generic kernel needs every row at once: the window is the grid
-    F.ring_planes = F.fB > 0 ? ring_planes_for(F, F.ldl) : n1;
+    const int64_t rowlen = F.fB > 0 ? F.ldr : F.ldl;   // window row: box positions, or row-major
+    F.ring_planes = F.fB > 0 ? ring_planes_for(F, rowlen) : n1;
     F.ring_rows = (int64_t)F.ring_planes * n1 * n1;
     F.sBX = 8;
     F.snxb = (n1 + F.sBX - 1) / F.sBX;
@@ -119,7 +140,7 @@ size_t plan_factor3(Factor& F, void* buf, int store) {
     F.L32 = F.Ut32 = nullptr;
     F.A64 = F.has64 ? c.take<double>((size_t)nlo * F.ldo) : nullptr;
     F.A32 = F.has32 ? c.take<float>((size_t)nlo * F.ldo) : nullptr;
-    F.ring = c.take<double>((size_t)(F.ring_rows + 1) * F.ldl);
+    F.ring = c.take<double>((size_t)(F.ring_rows + 1) * rowlen);
     F.Dg = c.take<double>(n);
     F.invD = c.take<double>(n);
     F.invD32 = F.has32 ? c.take<float>(n) : nullptr;
@@ -134,6 +155,10 @@ size_t plan_factor3(Factor& F, void* buf, int store) {
     F.steps = c.take<int>((size_t)4 * (nlo + 1));
     F.sdxyz = c.take<int>(nlo + 1);
     F.pairw = c.take<unsigned>((size_t)F.npairs + 64 * kPairsPerLane);
+    // pairs of the chunked kernel: two 16-bit positions per word, each step
+    // padded to a multiple of 128 pairs, then 64 Q zero words
+    F.pw16 = c.take<unsigned>(F.fB > 0 ? ((size_t)F.npairs + 128 * (size_t)(nlo + 1)) / 2 + 64 * kPairsPerLane : 1);
+    F.kofp = c.take<int>(F.fB > 0 ? (size_t)F.bP0 : 1);
     // packets: at most one per 64 pairs of each step, plus one per step
     F.pk = c.take<int>((size_t)4 * ((size_t)F.npairs / (64 * kPairsPerLane) + 2 * (size_t)nlo + 2));
     F.chunk_order = c.take<int>(F.nchunks > 0 ? F.nchunks : 1);
@@ -186,13 +211,15 @@ __global__ void fill_rows_kernel(double* __restrict__ ring, int64_t first, int64
 
 struct F3Args {
     int n1, nlo, ldl, T, h, lgB, nxb, npk, j0;
+    int X, XY, P0, PD;       // box positions: x extent, plane size, diagonal, 1/D slot (ldl: window row length)
     int64_t n, ring_rows, ldo;
     int ring_planes;
     int tk_begin, tk_end;
     const int4* pk;          // packets {first pair, count, packed (dx,dy,dz), j | first << 30 | last << 31}
-    const int2* jrange;      // [nlo] pair range of the step of offset j
+    const int2* jrange;      // [nlo] word range of the step of offset j
     const int4* offs;        // [nlo + 1] (dx, dy, dz, linear) in column order
-    const unsigned* pairw;   // [npairs + 64 Q] k*8 | (l*8) << 16
+    const unsigned* pairw;   // pair words: two byte offsets p(delta_l)*8, low half first
+    const int* kofp;         // [P0] lower offset index at each box position, or -1
     const int* chunk_order;
     const double* band;
     const double* fold;
@@ -222,12 +249,14 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
     const int n1 = a.n1, nlo = a.nlo, h = a.h;
     const int W = 2 * h + 1, T1 = a.T + 1, bandT = n1 * W;
     const int B = 1 << a.lgB;
-    double* u = smem3 + (size_t)wv * (nlo + 2);
+    const int X = a.X, XY = a.XY, P0 = a.P0, PD = a.PD;
+    double* u = smem3 + (size_t)wv * (P0 + 2);   // box positions 0 .. P0, then a zero slot
     const char* ub = (const char*)u;
     const int64_t zbase = a.ring_rows * (int64_t)a.ldl;   // the zero row
-    // lanes past a packet's pairs: u index nlo+1 (zero) and the first step's
-    // entry of the same row (published together with the needed ones)
-    const unsigned padw = (unsigned)(nlo + 1) * 8u | ((unsigned)a.j0 * 8u << 16);
+    // pairs past a packet's end: the neighbour row's diagonal slot, which the
+    // row publishes as zero together with its entries
+    const unsigned padh = (unsigned)P0 * 8u;
+    const unsigned padw = padh | (padh << 16);
     for (;;) {
         __syncthreads();
         if (tid == 0) {
@@ -246,27 +275,30 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
         const int64_t i = (int64_t)line * n1 + ix;
         const int64_t myslot = ring_slot(a, line, ix);
 
-        // M(i, i + delta_k) for the lower offsets and the diagonal (Kronecker
-        // form of Sec. 4.2 over the folded line coefficients); zero where the
-        // column leaves the grid
+        // u: zero, then M(i, i + delta_k) for the lower offsets and the
+        // diagonal (Kronecker form of Sec. 4.2 over the folded line
+        // coefficients) at their box positions; zero where the column leaves
+        // the grid
+        for (int p = lane; p <= P0 + 1; p += 64) u[p] = 0.0;
         for (int k = lane; k <= nlo; k += 64) {
             const int4 o = a.offs[k];
-            double v = 0.0;
             if ((unsigned)(ix + o.x) < (unsigned)n1 && (unsigned)(iy + o.y) < (unsigned)n1 &&
                 (unsigned)(iz + o.z) < (unsigned)n1) {
                 const double* pS = a.band + ix * W + (o.x + h);
                 const double* pF = a.fold + ((int64_t)line * W * W + (int64_t)(o.z + h) * W + (o.y + h)) * 2 * T1;
+                double v = 0.0;
                 for (int t = 0; t < T1; ++t) v += pS[t * bandT] * pF[t] + pS[(T1 + t) * bandT] * pF[T1 + t];
+                u[P0 + o.z * XY + o.y * X + o.x] = v;
             }
-            u[k] = v;
         }
-        if (lane == 0) u[nlo + 1] = 0.0;
 
+        constexpr int QW = Q / 2;   // pair words per lane per packet
         double g[PP][Q];
-        unsigned pw[PP][Q];
-        int jj[PP], lastp[PP];
+        unsigned pw[PP][QW];
+        int jj[PP], lastp[PP], us[PP];
         int64_t rb[PP];
         int64_t cur = zbase;   // ring row offset of the step being issued
+        int cur_s = 0;         // its shift p(delta_j) - P0, in bytes
         // Packet descriptors: lane t of `win` holds packet w0 + t and is read
         // with readlane (no scalar load in the loop); `nxt` collects packets
         // w0 + 64 .. w0 + 127, one lane per issued packet, from a load made
@@ -300,32 +332,37 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
             const bool live = p < a.npk;   // wave-uniform
             const int4 P = live ? Pd : make_int4(0, 0, 0, (int)(nlo + 1));
             if (!live) cur = zbase;
-            if (P.w & (1 << 30)) {   // first packet of a step: its row
+            if (P.w & (1 << 30)) {   // first packet of a step: its row and shift
                 const int dx = (P.z & 0xFF) - 128, dy = ((P.z >> 8) & 0xFF) - 128, dz = ((P.z >> 16) & 0xFF) - 128;
                 const bool valid = (unsigned)(ix + dx) < (unsigned)n1 && (unsigned)(iy + dy) < (unsigned)n1 &&
                                    (unsigned)(iz + dz) < (unsigned)n1;
                 cur = valid ? ring_slot(a, line + dy + dz * n1, ix + dx) * a.ldl : zbase;
+                cur_s = (dz * XY + dy * X + dx) * 8;
             }
             rb[b] = cur;
+            us[b] = cur_s;
             jj[b] = P.w & 0x3FFFFFFF;
             lastp[b] = (P.w >> 31) & 1;
+            // P.y: rows of 64 words (128 pairs) the packet holds
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const int e = lane + 64 * q;
-                const unsigned wd0 = a.pairw[P.x + e];
-                pw[b][q] = (e < P.y) ? wd0 : padw;
+            for (int q = 0; q < QW; ++q) {
+                const unsigned wd0 = a.pairw[P.x + lane + 64 * q];
+                pw[b][q] = (q < P.y) ? wd0 : padw;
             }
         };
         auto stage_b = [&](int b) {
             const char* rowp = (const char*)(a.ring + rb[b]);
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
-                g[b][q] = __hip_atomic_load((const double*)(rowp + (pw[b][q] >> 16)), __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (int q = 0; q < QW; ++q) {
+                g[b][2 * q] = __hip_atomic_load((const double*)(rowp + (pw[b][q] & 0xFFFFu)), __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+                g[b][2 * q + 1] = __hip_atomic_load((const double*)(rowp + (pw[b][q] >> 16)), __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         };
         // the whole step again with coherent loads, until none of its values
         // is the sentinel (a computed NaN ends the wait as well)
-        auto slow_step = [&](int j, int64_t base) {
+        auto slow_step = [&](int j, int64_t base, int sh) {
             const int2 R = a.jrange[j];
             for (;;) {
                 bool pend = false;
@@ -333,9 +370,11 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
                 for (int e0 = R.x; e0 < R.y || e0 == R.x; e0 += 64) {
                     const int e = e0 + lane;
                     const unsigned wd = (e < R.y) ? a.pairw[e] : padw;
-                    const double gv = ld_coh((const double*)((const char*)(a.ring + base) + (wd >> 16)));
-                    pend |= Sentinel<double>::is(gv);
-                    sum += *(const double*)(ub + (wd & 0xFFFFu)) * gv;
+                    const char* rowp = (const char*)(a.ring + base);
+                    const double g0 = ld_coh((const double*)(rowp + (wd & 0xFFFFu)));
+                    const double g1 = ld_coh((const double*)(rowp + (wd >> 16)));
+                    pend |= Sentinel<double>::is(g0) || Sentinel<double>::is(g1);
+                    sum += *(const double*)(ub + sh + (wd & 0xFFFFu)) * g0 + *(const double*)(ub + sh + (wd >> 16)) * g1;
                 }
                 if (!__any(pend)) return wave_total_bcast(sum);
                 __builtin_amdgcn_s_sleep(2);
@@ -344,17 +383,22 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
         double acc = 0.0;
         int nslow = 0;
         auto consume = [&](int b) {
+            const char* us_b = ub + us[b];   // u shifted by p(delta_j) - P0
 #pragma unroll
-            for (int q = 0; q < Q; ++q) acc += *(const double*)(ub + (pw[b][q] & 0xFFFFu)) * g[b][q];
+            for (int q = 0; q < QW; ++q) {
+                acc += *(const double*)(us_b + (pw[b][q] & 0xFFFFu)) * g[b][2 * q];
+                acc += *(const double*)(us_b + (pw[b][q] >> 16)) * g[b][2 * q + 1];
+            }
             if (lastp[b]) {   // wave-uniform
                 double tot = wave_total_bcast(acc);
                 acc = 0.0;
                 if (__builtin_expect(isnan(tot), 0)) {
-                    tot = slow_step(jj[b], rb[b]);
+                    tot = slow_step(jj[b], rb[b], us[b]);
                     ++nslow;
                 }
-                const double mj = u[jj[b]];
-                if (lane == 0) u[jj[b]] = mj - tot;
+                const int jpos = P0 + us[b] / 8;
+                const double mj = u[jpos];
+                if (lane == 0) u[jpos] = mj - tot;
             }
         };
         constexpr int PG = PP / 2;   // gathers in flight (packets)
@@ -371,42 +415,68 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
             }
         }
 
-        // L(i, i+delta_k) = u_k / D(i+delta_k); D(i) = M(i,i) - sum_k u_k L(i, i+delta_k)
+        // L(i, i + delta) = u(p) / D(i + delta), D(i) = M(i, i) - sum_p u(p) L(i, i + delta);
+        // the 1/D of FB positions per lane are loaded together, then checked
+        constexpr int FB = 8;
         double piv = 0.0;
-        for (int k = lane; k < nlo; k += 64) {
-            const int4 o = a.offs[k];
-            double dv = 0.0;
-            if ((unsigned)(ix + o.x) < (unsigned)n1 && (unsigned)(iy + o.y) < (unsigned)n1 &&
-                (unsigned)(iz + o.z) < (unsigned)n1) {
-                const double* pd = a.ring + ring_slot(a, line + o.y + o.z * n1, ix + o.x) * a.ldl + nlo;
-                dv = *pd;
-                while (Sentinel<double>::is(dv)) {
-                    __builtin_amdgcn_s_sleep(2);
-                    dv = ld_coh(pd);
+        for (int pb = 0; pb < P0; pb += 64 * FB) {
+            double dv[FB];
+            const double* pd[FB];
+#pragma unroll
+            for (int r = 0; r < FB; ++r) {
+                const int p = pb + lane + 64 * r;
+                pd[r] = nullptr;
+                dv[r] = 0.0;
+                if (p < P0) {
+                    const int k = a.kofp[p];
+                    if (k >= 0 && u[p] != 0.0) {
+                        const int4 o = a.offs[k];
+                        if ((unsigned)(ix + o.x) < (unsigned)n1 && (unsigned)(iy + o.y) < (unsigned)n1 &&
+                            (unsigned)(iz + o.z) < (unsigned)n1)
+                            pd[r] = a.ring + ring_slot(a, line + o.y + o.z * n1, ix + o.x) * a.ldl + PD;
+                    }
+                }
+                if (pd[r]) dv[r] = __hip_atomic_load(pd[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+#pragma unroll
+            for (int r = 0; r < FB; ++r) {
+                const int p = pb + lane + 64 * r;
+                if (p < P0) {
+                    if (pd[r]) {
+                        while (Sentinel<double>::is(dv[r])) {
+                            __builtin_amdgcn_s_sleep(2);
+                            dv[r] = ld_coh(pd[r]);
+                        }
+                    }
+                    const double uv = u[p];
+                    const double lk = pd[r] ? uv * dv[r] : 0.0;
+                    piv += uv * lk;
+                    u[p] = lk;
                 }
             }
-            const double lk = u[k] * dv;
-            piv += u[k] * lk;
-            u[k] = lk;
         }
         piv = wave_total_bcast(piv);
-        const double Dr = u[nlo] - piv;
+        const double Dr = u[P0] - piv;
         const double Dii = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(Dr)),
                                             __builtin_amdgcn_readfirstlane(__double2loint(Dr)));
         if (!(Dii > 0.0) || !isfinite(Dii)) {
             if (lane == 0) atomicOr(a.flag, 1);
         }
         const double iv = 1.0 / Dii;
+        // the row at its box positions (zero at holes, columns outside the
+        // grid and the slots up to 1/D), then 1/D
         double* rowp = a.ring + myslot * a.ldl;
-        for (int k = lane; k < nlo; k += 64) {
-            const double lk = u[k];
-            st_coh(rowp + k, Sentinel<double>::clean(lk));
-            if (a.A64) a.A64[(int64_t)k * a.ldo + i] = lk;
-            if (a.A32) a.A32[(int64_t)k * a.ldo + i] = (float)lk;
+        for (int p = lane; p < PD; p += 64) st_coh(rowp + p, p < P0 ? Sentinel<double>::clean(u[p]) : 0.0);
+        for (int p = lane; p < P0; p += 64) {
+            const int k = a.kofp[p];
+            if (k >= 0) {
+                if (a.A64) a.A64[(int64_t)k * a.ldo + i] = u[p];
+                if (a.A32) a.A32[(int64_t)k * a.ldo + i] = (float)u[p];
+            }
         }
         if (lane == 0 && nslow) atomicAdd(a.flag + 2, nslow);
         if (lane == 0) {
-            st_coh(rowp + nlo, Sentinel<double>::clean(iv));
+            st_coh(rowp + PD, Sentinel<double>::clean(iv));
             a.Dg[i] = Dii;
             a.invD[i] = iv;
             if (a.invD32) a.invD32[i] = (float)iv;
@@ -698,29 +768,57 @@ static lgp_status sweep3_tables(Factor& F, hipStream_t s, std::vector<int>& blk,
 // tables and folded coefficients computed, offsets, steps (dataflow order)
 // and pair words uploaded (pairw followed by 64 zero words). Synchronises
 // the stream before returning (the host tables go out of scope).
-lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hipEvent_t* ev) {
+lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, const std::vector<unsigned>& pw,
+                       hipEvent_t* ev) {
     const int n1 = F.n1, nlo = F.nlo, B = F.fB;
     if (B <= 0) return LGP_E_UNSUPPORTED;
     const int nsteps = nlo;
-    constexpr int Q = kPairsPerLane;
-    // packets of at most 64 Q pairs, step by step in dataflow order:
-    // {first pair, count, packed (dx, dy, dz), j | first << 30 | last << 31}
+    constexpr int Q = kPairsPerLane, QW = Q / 2;
+    const int X = F.bX, XY = F.bXY, P0 = F.bP0;
+    // box position of every lower offset
+    std::vector<int> kofp(P0, -1), posk(nlo);
+    for (int k = 0; k < nlo; ++k) {
+        const int* o = &F.offs[3 * k];
+        const int p = P0 + o[2] * XY + o[1] * X + o[0];
+        if (p < 0 || p >= P0 || kofp[p] >= 0) return LGP_E_UNSUPPORTED;
+        kofp[p] = k;
+        posk[k] = p;
+    }
+    // Pair words: the byte offset 8 p(delta_l) of each pair (u_k L(i+delta_j, i+delta_k),
+    // delta_k = delta_j + delta_l), two per word, each step padded to whole
+    // rows of 64 words with the diagonal position. Packets of up to QW rows,
+    // step by step in dataflow order:
+    // {first word, rows, packed (dx, dy, dz), j | first << 30 | last << 31}
+    const unsigned padh = (unsigned)P0 * 8u;
+    std::vector<unsigned> words;
+    words.reserve(pw.size() / 2 + 64 * (size_t)nsteps + 64 * Q);
     std::vector<int> pk, jr(2 * (size_t)(nlo + 1), 0);
     for (int st = 0; st < nsteps; ++st) {
         const int j = st4[4 * st], p0 = st4[4 * st + 2], p1 = st4[4 * st + 3];
         const int* o = &F.offs[3 * j];
         const int packed = (o[0] + 128) | ((o[1] + 128) << 8) | ((o[2] + 128) << 16);
         const int np = p1 - p0;
-        const int npk = std::max(1, (np + 64 * Q - 1) / (64 * Q));
+        const int rows = std::max(1, (np + 127) / 128);
+        const int w0 = (int)words.size();
+        for (int e = 0; e < rows * 128; e += 2) {
+            const unsigned lo = p0 + e < p1 ? (unsigned)posk[(pw[p0 + e] >> 16) / 8u] * 8u : padh;
+            const unsigned hi = p0 + e + 1 < p1 ? (unsigned)posk[(pw[p0 + e + 1] >> 16) / 8u] * 8u : padh;
+            words.push_back(lo | (hi << 16));
+        }
+        const int npk = (rows + QW - 1) / QW;
         for (int q = 0; q < npk; ++q) {
             const unsigned fl = (unsigned)j | (q == 0 ? 1u << 30 : 0u) | (q == npk - 1 ? 1u << 31 : 0u);
-            pk.insert(pk.end(), {p0 + 64 * Q * q, std::max(0, std::min(64 * Q, np - 64 * Q * q)), packed, (int)fl});
+            pk.insert(pk.end(), {w0 + 64 * QW * q, std::min(QW, rows - QW * q), packed, (int)fl});
         }
-        jr[2 * j] = p0;
-        jr[2 * j + 1] = p1;
+        jr[2 * j] = w0;
+        jr[2 * j + 1] = w0 + 64 * rows;
     }
+    words.insert(words.end(), 64 * Q, 0u);
     F.npk = (int)pk.size() / 4;
     if ((size_t)F.npk > (size_t)F.npairs / (64 * Q) + 2 * (size_t)nlo + 2) return LGP_E_ARG;   // planner disagrees
+    if (words.size() > ((size_t)F.npairs + 128 * (size_t)(nlo + 1)) / 2 + 64 * Q) return LGP_E_ARG;
+    LGP_HIP(hipMemcpyAsync(F.pw16, words.data(), words.size() * 4, hipMemcpyHostToDevice, s));
+    LGP_HIP(hipMemcpyAsync(F.kofp, kofp.data(), kofp.size() * 4, hipMemcpyHostToDevice, s));
     // chunk order and ranks
     const ChunkKeys K = chunk_keys(B, F.Hx, F.Hy, F.Hz);
     std::vector<int> order, keystart;
@@ -762,12 +860,17 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
     }
     // zero row, then per launch: sentinel into its slots, reset the ticket, run
     const int64_t R = F.ring_rows;
-    hipLaunchKernelGGL(fill_rows_kernel, dim3(64), dim3(256), 0, s, F.ring, R, (int64_t)1, F.ldl, 0.0);
+    hipLaunchKernelGGL(fill_rows_kernel, dim3(64), dim3(256), 0, s, F.ring, R, (int64_t)1, F.ldr, 0.0);
     LGP_HIP(hipMemsetAsync(F.flag, 0, 16, s));
     F3Args a;
     a.n1 = n1;
     a.nlo = nlo;
-    a.ldl = F.ldl;
+    a.ldl = F.ldr;   // window row length
+    a.X = X;
+    a.XY = XY;
+    a.P0 = P0;
+    a.PD = F.bPD;
+    a.kofp = F.kofp;
     a.T = F.T;
     a.h = F.h;
     a.lgB = 0;
@@ -782,7 +885,7 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
     a.pk = (const int4*)F.pk;
     a.jrange = (const int2*)F.pair_ptr;
     a.offs = (const int4*)F.d_offs;
-    a.pairw = F.pairw;
+    a.pairw = F.pw16;
     a.chunk_order = F.chunk_order;
     a.band = F.band;
     a.fold = F.fold3;
@@ -797,7 +900,7 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
     auto kf = ilu3d_factor_kernel<Q, 4>;
     if (const char* e = std::getenv("LGP_F3_PP"))
         if (std::atoi(e) == 8) kf = ilu3d_factor_kernel<Q, 8>;
-    const size_t shmem = (size_t)B * (nlo + 2) * 8;
+    const size_t shmem = (size_t)B * (P0 + 2) * 8;
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (ev) (void)hipEventRecord(ev[0], s);
     for (auto& L : launches) {
@@ -807,7 +910,7 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, hi
             memcpy(&sen, &bits, 8);
         }
         hipLaunchKernelGGL(fill_chunk_rows_kernel, dim3(4096), dim3(256), 0, s, F.ring, (const int*)F.chunk_order,
-                           L.first, L.second, B, F.nxb, n1, Z, F.ldl, sen);
+                           L.first, L.second, B, F.nxb, n1, Z, F.ldr, sen);
         hipLaunchKernelGGL(reset3_kernel, dim3(1), dim3(64), 0, s, F.ticket, 4);
         a.tk_begin = L.first;
         a.tk_end = L.second;

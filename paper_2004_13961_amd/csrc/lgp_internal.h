@@ -196,6 +196,11 @@ struct Factor {
     int* blk_order = nullptr;     // [nlines * snxb] substitution blocks in dependency order
     int* own = nullptr;           // [8] offset index of (-m, 0, 0), m = 1..8 (-1 if absent)
     double* fold3 = nullptr;      // folded line coefficients of the 3D path
+    // box positions of the chunked 3D kernel (u vectors and window rows)
+    int bX = 0, bXY = 0, bP0 = 0, bPD = 0;   // x extent, plane size, diagonal position, 1/D slot
+    int ldr = 0;                  // window row length (doubles)
+    unsigned* pw16 = nullptr;     // pair positions, two 16-bit byte offsets per word
+    int* kofp = nullptr;          // [bP0] lower offset index at each box position, or -1
 };
 
 // One slot of a batched substitution: the operator and vectors of one
