@@ -2,10 +2,11 @@
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
-Alg. 1 as printed: r = F - K x; while ||r||_2 > eps ||F||_2 and k < k_max:
-solve M z = r (here: the preconditioner callback), k = k + 1, p = z on the
-first step, else rho~ = rho, rho = r.z, beta = rho/rho~, p = z + beta p;
-w = K p, alpha = rho / p.w, x = x + alpha p, r = r - alpha w.
+The textbook preconditioned conjugate gradient method for a symmetric
+positive definite K with preconditioner M (Alg. 1 of the paper): the search
+direction is the preconditioned residual made K-conjugate to the previous
+direction, and the iteration stops once the recursive residual's 2-norm
+falls to eps times that of F, or after k_max iterations.
 Readings: x_0 = 0 unless given; k_max defaults to 2000; the test is on the
 recursive residual r.
 """

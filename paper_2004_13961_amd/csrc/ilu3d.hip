@@ -33,16 +33,22 @@
 // columns outside the grid and up to slot PD), and 1/D(r) at slot PD.
 //
 // Each row is computed left-looking (reading R1): u_j = M(i, i+d_j) -
-// sum over pairs (k, l) with d_k = d_j + d_l of u_k L(i+d_j, i+d_k), the
-// offsets j taken in the host's dataflow order; then L(i, i+d_j) = u_j /
-// D(i+d_j), D(i) = M(i,i) - sum_j u_j L(i, i+d_j). The row's u vector sits in
-// LDS at the same box positions, so p(d_k) = p(d_l) + p(d_j) - P0 and a pair
-// is the single byte offset 8 p(d_l): two pairs per 32-bit word. The pairs
-// of all steps form one list (each step padded to 128 pairs with P0, whose
-// window slot is zero) cut into packets of 512 (8 per lane); the loads of
-// the next PP packets are in flight while a packet is consumed. A row's
-// entries are published together when it is done; a gathered sentinel sends
-// the step to coherent re-reads.
+// sum over pairs (k, l) with d_k = d_j + d_l of u_k L(i+d_j, i+d_k); then
+// L(i, i+d_j) = u_j / D(i+d_j), D(i) = M(i,i) - sum_j u_j L(i, i+d_j). The
+// offsets j are taken grid line by grid line, the line taken longest ago
+// first and the row's own line last, x ascending within a line, so
+// consecutive steps read x-neighbouring rows of the window (a quarter less
+// traffic beyond the L2 than an order by hyperplane level). The row's u vector sits in
+// LDS at the same box positions, so p(d_k) = p(d_l) + p(d_j) - P0, and a
+// pair is named by p(d_l) alone. Pairs at adjacent positions p, p + 1 form a
+// duo, which one 16-byte load gathers and one LDS read pairs with u (a pair
+// without a neighbour is a duo with a flagged, zeroed second term); a duo is
+// the 16-bit value 8 p | flag, two per 32-bit word. The duos of all steps
+// form one list (each step padded to rows of 128 with P0, whose window slot
+// is zero) cut into packets of two rows; the loads of the next packets are
+// in flight while a packet is consumed. A row's entries are published
+// together when it is done; a gathered sentinel sends the step to coherent
+// re-reads.
 //
 // Substitution schedule. Blocks of BX consecutive rows of a line; a
 // workgroup (256 threads: BX rows x 256/BX offset groups) sums the terms of
@@ -78,7 +84,7 @@ static ChunkKeys chunk_keys(int B, int Hx, int Hy, int Hz) {
 // waves per workgroup of the 3D factor kernel: each wave holds its row's
 // u vector (n_lower + 2 doubles) in LDS
 // pairs per lane in one packet of the 3D factor kernel
-constexpr int kPairsPerLane = 8;
+constexpr int kRowsPerPacket = 2;   // rows of 64 duo words in a packet of the 3D factor kernel
 
 // The chunked kernel lays out each row's u vector (LDS) and the rows of the
 // window by position in the lower half of the stencil's bounding box,
@@ -154,13 +160,13 @@ size_t plan_factor3(Factor& F, void* buf, int store) {
     F.fold3 = c.take<double>((size_t)F.nlines * W * W * 2 * T1);
     F.steps = c.take<int>((size_t)4 * (nlo + 1));
     F.sdxyz = c.take<int>(nlo + 1);
-    F.pairw = c.take<unsigned>((size_t)F.npairs + 64 * kPairsPerLane);
+    F.pairw = c.take<unsigned>((size_t)F.npairs + 64 * 8);
     // pairs of the chunked kernel: two 16-bit positions per word, each step
     // padded to a multiple of 128 pairs, then 64 Q zero words
-    F.pw16 = c.take<unsigned>(F.fB > 0 ? ((size_t)F.npairs + 128 * (size_t)(nlo + 1)) / 2 + 64 * kPairsPerLane : 1);
+    F.pw16 = c.take<unsigned>(F.fB > 0 ? ((size_t)F.npairs + 128 * (size_t)(nlo + 1)) / 2 + 64 * kRowsPerPacket : 1);
     F.kofp = c.take<int>(F.fB > 0 ? (size_t)F.bP0 : 1);
     // packets: at most one per 64 pairs of each step, plus one per step
-    F.pk = c.take<int>((size_t)4 * ((size_t)F.npairs / (64 * kPairsPerLane) + 2 * (size_t)nlo + 2));
+    F.pk = c.take<int>((size_t)4 * ((size_t)F.npairs / 128 + 2 * (size_t)nlo + 2));
     F.chunk_order = c.take<int>(F.nchunks > 0 ? F.nchunks : 1);
     F.blk_order = c.take<int>((size_t)F.nlines * F.snxb);
     F.own = c.take<int>(16);
@@ -210,7 +216,7 @@ __global__ void fill_rows_kernel(double* __restrict__ ring, int64_t first, int64
 }
 
 struct F3Args {
-    int n1, nlo, ldl, T, h, lgB, nxb, npk, j0;
+    int n1, nlo, ldl, T, h, lgB, nxb, npk;
     int X, XY, P0, PD;       // box positions: x extent, plane size, diagonal, 1/D slot (ldl: window row length)
     int64_t n, ring_rows, ldo;
     int ring_planes;
@@ -218,7 +224,7 @@ struct F3Args {
     const int4* pk;          // packets {first pair, count, packed (dx,dy,dz), j | first << 30 | last << 31}
     const int2* jrange;      // [nlo] word range of the step of offset j
     const int4* offs;        // [nlo + 1] (dx, dy, dz, linear) in column order
-    const unsigned* pairw;   // pair words: two byte offsets p(delta_l)*8, low half first
+    const unsigned* pairw;   // duo words: two duos (byte offset 8 p | one-pair flag), low half first
     const int* kofp;         // [P0] lower offset index at each box position, or -1
     const int* chunk_order;
     const double* band;
@@ -239,8 +245,12 @@ __device__ inline int64_t ring_slot(const F3Args& a, int rl, int rx) {
     return ((int64_t)(rz % a.ring_planes) * a.n1 + ry) * a.n1 + rx;
 }
 
-// Q pairs per lane per packet (packets of up to 64 Q pairs), PP packets in flight
-template <int Q, int PP>
+// two adjacent doubles, at 8-byte alignment (one 16-byte load)
+typedef double dbl2u __attribute__((ext_vector_type(2), aligned(8)));
+
+// QW rows of 64 duo words per packet (4 QW duos, up to 8 QW pairs, per
+// lane), PP packets in flight, the gathers of PG of them
+template <int QW, int PP, int PG>
 __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
     extern __shared__ double smem3[];
     __shared__ int s_chunk, s_rank;
@@ -253,9 +263,9 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
     double* u = smem3 + (size_t)wv * (P0 + 2);   // box positions 0 .. P0, then a zero slot
     const char* ub = (const char*)u;
     const int64_t zbase = a.ring_rows * (int64_t)a.ldl;   // the zero row
-    // pairs past a packet's end: the neighbour row's diagonal slot, which the
-    // row publishes as zero together with its entries
-    const unsigned padh = (unsigned)P0 * 8u;
+    // duos past a packet's end: the neighbour row's diagonal slot, which the
+    // row publishes as zero together with its entries, second element absent
+    const unsigned padh = (unsigned)P0 * 8u | 1u;
     const unsigned padw = padh | (padh << 16);
     for (;;) {
         __syncthreads();
@@ -292,8 +302,7 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
             }
         }
 
-        constexpr int QW = Q / 2;   // pair words per lane per packet
-        double g[PP][Q];
+        dbl2u g[PP][2 * QW];
         unsigned pw[PP][QW];
         int jj[PP], lastp[PP], us[PP];
         int64_t rb[PP];
@@ -343,22 +352,29 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
             us[b] = cur_s;
             jj[b] = P.w & 0x3FFFFFFF;
             lastp[b] = (P.w >> 31) & 1;
-            // P.y: rows of 64 words (128 pairs) the packet holds
+            // P.y: rows of 64 words (128 duos) the packet holds
 #pragma unroll
             for (int q = 0; q < QW; ++q) {
                 const unsigned wd0 = a.pairw[P.x + lane + 64 * q];
                 pw[b][q] = (q < P.y) ? wd0 : padw;
             }
         };
+        // one 16-byte load per duo: the entries at its position and the next
         auto stage_b = [&](int b) {
             const char* rowp = (const char*)(a.ring + rb[b]);
 #pragma unroll
             for (int q = 0; q < QW; ++q) {
-                g[b][2 * q] = __hip_atomic_load((const double*)(rowp + (pw[b][q] & 0xFFFFu)), __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_WORKGROUP);
-                g[b][2 * q + 1] = __hip_atomic_load((const double*)(rowp + (pw[b][q] >> 16)), __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+                g[b][2 * q] = *(const dbl2u*)(rowp + (pw[b][q] & 0xFFFEu));
+                g[b][2 * q + 1] = *(const dbl2u*)(rowp + ((pw[b][q] >> 16) & 0xFFFEu));
             }
+        };
+        // a duo's two terms: u at the position (shifted by p(delta_j) - P0)
+        // and the next one, times the gathered pair; the second term is zero
+        // when the duo holds one pair (flag bit 0)
+        auto duo = [&](double s, const char* us_b, unsigned d, double gx, double gy) {
+            const char* up = us_b + (d & 0xFFFEu);
+            s = __builtin_fma(*(const double*)up, gx, s);
+            return __builtin_fma(*(const double*)(up + 8), (d & 1u) ? 0.0 : gy, s);
         };
         // the whole step again with coherent loads, until none of its values
         // is the sentinel (a computed NaN ends the wait as well)
@@ -371,10 +387,16 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
                     const int e = e0 + lane;
                     const unsigned wd = (e < R.y) ? a.pairw[e] : padw;
                     const char* rowp = (const char*)(a.ring + base);
-                    const double g0 = ld_coh((const double*)(rowp + (wd & 0xFFFFu)));
-                    const double g1 = ld_coh((const double*)(rowp + (wd >> 16)));
-                    pend |= Sentinel<double>::is(g0) || Sentinel<double>::is(g1);
-                    sum += *(const double*)(ub + sh + (wd & 0xFFFFu)) * g0 + *(const double*)(ub + sh + (wd >> 16)) * g1;
+#pragma unroll
+                    for (int hf = 0; hf < 2; ++hf) {
+                        const unsigned d = hf ? wd >> 16 : wd & 0xFFFFu;
+                        const double* gp = (const double*)(rowp + (d & 0xFFFEu));
+                        const double gx = ld_coh(gp), gy = ld_coh(gp + 1);
+                        pend |= Sentinel<double>::is(gx) || (!(d & 1u) && Sentinel<double>::is(gy));
+                        // the same operations in the same order as the packets
+                        // below, so a step gives the same bits on either path
+                        sum = duo(sum, ub + sh, d, gx, gy);
+                    }
                 }
                 if (!__any(pend)) return wave_total_bcast(sum);
                 __builtin_amdgcn_s_sleep(2);
@@ -386,8 +408,8 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
             const char* us_b = ub + us[b];   // u shifted by p(delta_j) - P0
 #pragma unroll
             for (int q = 0; q < QW; ++q) {
-                acc += *(const double*)(us_b + (pw[b][q] & 0xFFFFu)) * g[b][2 * q];
-                acc += *(const double*)(us_b + (pw[b][q] >> 16)) * g[b][2 * q + 1];
+                acc = duo(acc, us_b, pw[b][q] & 0xFFFFu, g[b][2 * q].x, g[b][2 * q].y);
+                acc = duo(acc, us_b, pw[b][q] >> 16, g[b][2 * q + 1].x, g[b][2 * q + 1].y);
             }
             if (lastp[b]) {   // wave-uniform
                 double tot = wave_total_bcast(acc);
@@ -401,7 +423,6 @@ __global__ __launch_bounds__(512) void ilu3d_factor_kernel(F3Args a) {
                 if (lane == 0) u[jpos] = mj - tot;
             }
         };
-        constexpr int PG = PP / 2;   // gathers in flight (packets)
 #pragma unroll
         for (int b = 0; b < PP; ++b) stage_a(b, b);
 #pragma unroll
@@ -773,7 +794,7 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, co
     const int n1 = F.n1, nlo = F.nlo, B = F.fB;
     if (B <= 0) return LGP_E_UNSUPPORTED;
     const int nsteps = nlo;
-    constexpr int Q = kPairsPerLane, QW = Q / 2;
+    constexpr int QW = kRowsPerPacket;
     const int X = F.bX, XY = F.bXY, P0 = F.bP0;
     // box position of every lower offset
     std::vector<int> kofp(P0, -1), posk(nlo);
@@ -784,27 +805,59 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, co
         kofp[p] = k;
         posk[k] = p;
     }
-    // Pair words: the byte offset 8 p(delta_l) of each pair (u_k L(i+delta_j, i+delta_k),
-    // delta_k = delta_j + delta_l), two per word, each step padded to whole
-    // rows of 64 words with the diagonal position. Packets of up to QW rows,
-    // step by step in dataflow order:
+    // Step order: grid lines of the offsets from the one taken longest ago
+    // (largest key lag -(wy dy + wz dz)) to the row's own line, x ascending
+    // within a line. A pair's u_k lies on a line of larger lag, or on the
+    // same line at smaller dx, so this is an order of the dependencies
+    // (checked below); consecutive steps read x-neighbouring rows, which the
+    // chunk's next row reads one step earlier, so more of a row's gathers
+    // find the L2 lines its neighbour brought in.
+    const ChunkKeys K = chunk_keys(B, F.Hx, F.Hy, F.Hz);
+    std::vector<int> ord(nsteps), rank(nlo, -1);
+    for (int st = 0; st < nsteps; ++st) ord[st] = st;
+    auto lag = [&](int st) {
+        const int* o = &F.offs[3 * st4[4 * st]];
+        return -(K.wy * o[1] + K.wz * o[2]);
+    };
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+        const int lx = lag(x), ly = lag(y);
+        return lx != ly ? lx > ly : F.offs[3 * st4[4 * x]] < F.offs[3 * st4[4 * y]];
+    });
+    for (int st = 0; st < nsteps; ++st) rank[st4[4 * ord[st]]] = st;
+    for (int st = 0; st < nsteps; ++st)
+        for (int e = st4[4 * ord[st] + 2]; e < st4[4 * ord[st] + 3]; ++e)
+            if (rank[(pw[e] & 0xFFFFu) / 8u] >= st) return LGP_E_ARG;   // u_k would not be ready
+    // Duo words. The pairs of a step (u_k L(i+delta_j, i+delta_k), delta_k =
+    // delta_j + delta_l) are cut into duos: two pairs at adjacent positions
+    // p(delta_l) = p and p + 1, or one pair alone (flag bit 0 set); a duo is
+    // the 16-bit byte offset 8 p | flag, and one 16-byte load gathers it.
+    // Word t of a row of 64 holds duos t and 64 + t of the row's 128, so
+    // each of a row's two gathers reads 64 consecutive duos. Each step is
+    // padded to whole rows with the diagonal position (flagged). Packets of
+    // up to QW rows, step by step in that order:
     // {first word, rows, packed (dx, dy, dz), j | first << 30 | last << 31}
-    const unsigned padh = (unsigned)P0 * 8u;
-    std::vector<unsigned> words;
-    words.reserve(pw.size() / 2 + 64 * (size_t)nsteps + 64 * Q);
+    const unsigned padh = (unsigned)P0 * 8u | 1u;
+    std::vector<unsigned> words, duos;
+    words.reserve(pw.size() / 2 + 64 * (size_t)nsteps + 64 * QW);
     std::vector<int> pk, jr(2 * (size_t)(nlo + 1), 0);
-    for (int st = 0; st < nsteps; ++st) {
+    for (int sti = 0; sti < nsteps; ++sti) {
+        const int st = ord[sti];
         const int j = st4[4 * st], p0 = st4[4 * st + 2], p1 = st4[4 * st + 3];
         const int* o = &F.offs[3 * j];
         const int packed = (o[0] + 128) | ((o[1] + 128) << 8) | ((o[2] + 128) << 16);
-        const int np = p1 - p0;
-        const int rows = std::max(1, (np + 127) / 128);
-        const int w0 = (int)words.size();
-        for (int e = 0; e < rows * 128; e += 2) {
-            const unsigned lo = p0 + e < p1 ? (unsigned)posk[(pw[p0 + e] >> 16) / 8u] * 8u : padh;
-            const unsigned hi = p0 + e + 1 < p1 ? (unsigned)posk[(pw[p0 + e + 1] >> 16) / 8u] * 8u : padh;
-            words.push_back(lo | (hi << 16));
+        duos.clear();
+        for (int e = p0; e < p1;) {
+            const unsigned pa = (unsigned)posk[(pw[e] >> 16) / 8u];
+            const bool two = e + 1 < p1 && (unsigned)posk[(pw[e + 1] >> 16) / 8u] == pa + 1;
+            duos.push_back(pa * 8u | (two ? 0u : 1u));
+            e += two ? 2 : 1;
         }
+        const int nd = (int)duos.size();
+        const int rows = std::max(1, (nd + 127) / 128);
+        const int w0 = (int)words.size();
+        auto db = [&](int e) { return e < nd ? duos[e] : padh; };
+        for (int m = 0; m < rows; ++m)
+            for (int t = 0; t < 64; ++t) words.push_back(db(128 * m + t) | (db(128 * m + 64 + t) << 16));
         const int npk = (rows + QW - 1) / QW;
         for (int q = 0; q < npk; ++q) {
             const unsigned fl = (unsigned)j | (q == 0 ? 1u << 30 : 0u) | (q == npk - 1 ? 1u << 31 : 0u);
@@ -813,14 +866,13 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, co
         jr[2 * j] = w0;
         jr[2 * j + 1] = w0 + 64 * rows;
     }
-    words.insert(words.end(), 64 * Q, 0u);
+    words.insert(words.end(), 64 * QW, 0u);   // the rows a last packet loads past its step
     F.npk = (int)pk.size() / 4;
-    if ((size_t)F.npk > (size_t)F.npairs / (64 * Q) + 2 * (size_t)nlo + 2) return LGP_E_ARG;   // planner disagrees
-    if (words.size() > ((size_t)F.npairs + 128 * (size_t)(nlo + 1)) / 2 + 64 * Q) return LGP_E_ARG;
+    if ((size_t)F.npk > (size_t)F.npairs / 128 + 2 * (size_t)nlo + 2) return LGP_E_ARG;   // planner disagrees
+    if (words.size() > ((size_t)F.npairs + 128 * (size_t)(nlo + 1)) / 2 + 64 * kRowsPerPacket) return LGP_E_ARG;
     LGP_HIP(hipMemcpyAsync(F.pw16, words.data(), words.size() * 4, hipMemcpyHostToDevice, s));
     LGP_HIP(hipMemcpyAsync(F.kofp, kofp.data(), kofp.size() * 4, hipMemcpyHostToDevice, s));
     // chunk order and ranks
-    const ChunkKeys K = chunk_keys(B, F.Hx, F.Hy, F.Hz);
     std::vector<int> order, keystart;
     key_order(n1, F.nxb, K, order, &keystart);
     std::vector<int> blk, own;
@@ -877,7 +929,6 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, co
     while ((1 << a.lgB) < B) ++a.lgB;
     a.nxb = F.nxb;
     a.npk = F.npk;
-    a.j0 = st4[0];
     a.n = F.n;
     a.ring_rows = R;
     a.ring_planes = Z;
@@ -897,9 +948,9 @@ lgp_status factor3_run(Factor& F, hipStream_t s, const std::vector<int>& st4, co
     a.invD32 = F.invD32;
     a.ticket = F.ticket;
     a.flag = F.flag;
-    auto kf = ilu3d_factor_kernel<Q, 4>;
-    if (const char* e = std::getenv("LGP_F3_PP"))
-        if (std::atoi(e) == 8) kf = ilu3d_factor_kernel<Q, 8>;
+    // two rows per packet, six packets in flight, the gathers of four (of
+    // the depths that fit two waves per SIMD, the fastest measured)
+    auto kf = ilu3d_factor_kernel<kRowsPerPacket, 6, 4>;
     const size_t shmem = (size_t)B * (P0 + 2) * 8;
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (ev) (void)hipEventRecord(ev[0], s);

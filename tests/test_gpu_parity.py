@@ -85,8 +85,11 @@ def _oracle_factor(d, N, a, b, Ta, Tb):
     return st, offs
 
 
+# 3D: N = 7, 10, 12 are narrower than twice the stencil's reach (generic
+# kernel); N = 14 and 18 take the chunked kernel, with a part-filled last
+# chunk on every line (13 = 8 + 5 and 17 = 2 x 8 + 1 rows)
 FACTOR_CASES = [(2, 12, 4, 4, 0), (2, 33, 4, 4, 0), (2, 40, 8, 8, 1), (2, 50, 6, 3, 2),
-                (3, 7, 2, 2, 0), (3, 10, 4, 4, 1), (3, 12, 6, 6, 2)]
+                (3, 7, 2, 2, 0), (3, 10, 4, 4, 1), (3, 12, 6, 6, 2), (3, 14, 2, 2, 1), (3, 18, 6, 6, 2)]
 
 
 # the ILU(0) kernel variants: 2 (dataflow, the default where it applies) and
@@ -115,6 +118,9 @@ def test_factor_and_sweeps(d, N, Ta, Tb, seed, kernel, monkeypatch):
     print("factor kernel %d" % desc["factor_kernel"], flush=True)
     if kernel:
         assert desc["factor_kernel"] == kernel
+    elif d == 3:   # the chunked kernel wherever the grid is wider than twice the reach in x and y
+        reach = max(max(abs(o[0]), abs(o[1])) for o in offs)
+        assert desc["factor_kernel"] == (3 if N - 1 > 2 * reach else 1)
     assert [tuple(o[:d]) for o in desc["offsets"]] == [tuple(o) for o in offs]
     nlo = desc["n_lower"]
     Lg = _host(desc["L"])
