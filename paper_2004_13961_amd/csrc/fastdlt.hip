@@ -211,21 +211,47 @@ static lgp_status upload_dlt(Dlt& D, hipStream_t s) {
 // ------------------------------------------------------------ FFT --------
 // In place, input in bit-reversed order, output natural:
 // X[t] = sum_v x[v] e^{+2 pi i v t / L}. 256 threads, L <= kDltMaxL.
-__device__ inline void fft_lds(double2* X, int L, int lgL, const double2* __restrict__ tw) {
-    for (int s = 0; s < lgL; ++s) {
-        const int h = 1 << s;
-        const int step = L >> (s + 1);   // twiddle stride
-        for (int b = threadIdx.x; b < L / 2; b += kDltT) {
-            const int pos = b & (h - 1);
-            const int i = ((b >> s) << (s + 1)) + pos;
-            const double2 w = tw[pos * step];
-            const double2 u = X[i], v = X[i + h];
-            const double2 t = make_double2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
-            X[i] = make_double2(u.x + t.x, u.y + t.y);
-            X[i + h] = make_double2(u.x - t.x, u.y - t.y);
+// Radix-2 butterflies, stage s pairing elements h = 2^s apart with the
+// twiddle of their position p in the pair's block, tw[p L / 2h]. R
+// consecutive stages are taken in one pass over LDS: the 2^R elements
+// base + m h (m < 2^R) that those stages combine only with each other sit
+// in registers while the same butterflies run on them in the same order,
+// so a pass replaces R rounds of LDS traffic and barriers.
+template <int R>
+__device__ inline void fft_pass(double2* X, int L, int s, const double2* __restrict__ tw) {
+    constexpr int E = 1 << R;
+    const int h = 1 << s;
+    for (int g = threadIdx.x; g < (L >> R); g += kDltT) {
+        const int pos0 = g & (h - 1);
+        const int base = ((g >> s) << (s + R)) + pos0;
+        double2 v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = X[base + m * h];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int step = L >> (s + t + 1);   // twiddle stride of stage s + t
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                if (m & (1 << t)) continue;
+                const int p = pos0 + (m & ((1 << t) - 1)) * h;   // position in the pair's block
+                const double2 w = tw[p * step];
+                const double2 u = v[m], x = v[m + (1 << t)];
+                const double2 tt = make_double2(w.x * x.x - w.y * x.y, w.x * x.y + w.y * x.x);
+                v[m] = make_double2(u.x + tt.x, u.y + tt.y);
+                v[m + (1 << t)] = make_double2(u.x - tt.x, u.y - tt.y);
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) X[base + m * h] = v[m];
     }
+    __syncthreads();
+}
+
+__device__ inline void fft_lds(double2* X, int L, int lgL, const double2* __restrict__ tw) {
+    int s = 0;
+    for (; s + 3 <= lgL; s += 3) fft_pass<3>(X, L, s, tw);
+    if (lgL - s == 2) fft_pass<2>(X, L, s, tw);
+    if (lgL - s == 1) fft_pass<1>(X, L, s, tw);
 }
 
 __device__ inline int bitrev(int v, int lg) { return (int)(__brev((unsigned)v) >> (32 - lg)); }
