@@ -473,30 +473,32 @@ __global__ __launch_bounds__(kDltT) void dlt_fwd_asym_kernel(int q, int L, int l
             T[fr] = make_double2(0.0, 0.0);
             pw[fr] = 1.0;
         }
+        // y_k = z_{m,k} (i delta_k hw)^p / p!, from p = 0, advanced by one
+        // complex product per Taylor term
+        double yr[kDltMaxNode], yi[kDltMaxNode], zd[kDltMaxNode];
+        for (int r = 0; r < kDltMaxNode; ++r) {
+            yr[r] = yi[r] = zd[r] = 0.0;
+            if (bpos[r] < 0) continue;
+            const int k = threadIdx.x + r * kDltT;
+            const double thk = D.th[k];
+            const double amp = vk[r] * std::pow(2.0 * D.sn[k], -(m + 0.5));
+            const double ph = (nc + m + 0.5) * thk;
+            yr[r] = amp * std::cos(ph);
+            yi[r] = amp * std::sin(ph);
+            zd[r] = D.dl[k] * hw;
+        }
         for (int p = 0; p < K; ++p) {
             for (int t = threadIdx.x; t < L; t += kDltT) X[t] = make_double2(0.0, 0.0);
             __syncthreads();
-            // spread z_{m,k} (i delta_k hw)^p / p! to the grid
+            // spread y_k to the grid, then y_k *= i z_k / (p + 1)
             for (int r = 0; r < kDltMaxNode; ++r) {
                 if (bpos[r] < 0) continue;
-                const int k = threadIdx.x + r * kDltT;
-                const double thk = D.th[k];
-                const double amp = vk[r] * std::pow(2.0 * D.sn[k], -(m + 0.5));
-                const double ph = (nc + m + 0.5) * thk;
-                double zr = amp * std::cos(ph), zi = amp * std::sin(ph);
-                const double z = D.dl[k] * hw;
-                double mag = 1.0;
-                for (int t = 1; t <= p; ++t) mag *= z / t;
-                double cr, ci;
-                switch (p & 3) {
-                    case 0: cr = mag; ci = 0.0; break;
-                    case 1: cr = 0.0; ci = mag; break;
-                    case 2: cr = -mag; ci = 0.0; break;
-                    default: cr = 0.0; ci = -mag; break;
-                }
-                const double yr = zr * cr - zi * ci, yi = zr * ci + zi * cr;
-                atomicAdd(&X[bpos[r]].x, yr);
-                atomicAdd(&X[bpos[r]].y, yi);
+                atomicAdd(&X[bpos[r]].x, yr[r]);
+                atomicAdd(&X[bpos[r]].y, yi[r]);
+                const double c = zd[r] / (p + 1);
+                const double nr = -yi[r] * c, ni = yr[r] * c;
+                yr[r] = nr;
+                yi[r] = ni;
             }
             __syncthreads();
             fft_lds(X, L, lgL, D.tw);
