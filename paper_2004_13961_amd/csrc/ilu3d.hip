@@ -609,18 +609,40 @@ __global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
         const int line = blk / a.nxb;
         const int x0 = (blk - line * a.nxb) * BXM;
         const int iy = line % n1, iz = line / n1;
+        // in-line coefficients and the right-hand side: independent of the
+        // wait below, so their loads go out first
+        if (tid < BXM * MO) {
+            const int rr = tid / MO, m = tid % MO;   // coefficient of (-(m+1), 0, 0) for row rr
+            const int k = a.own[m];
+            const int xx = x0 + rr;
+            T c = T(0);
+            if (k >= 0 && xx < n1 && xx - (m + 1) >= 0) {
+                const int64_t ipr = (int64_t)line * n1 + xx;
+                c = A[(int64_t)k * a.ldo + (REV ? mem(ipr - (m + 1)) : mem(ipr))];
+            }
+            s_coef[rr][m] = c;
+        } else if (tid >= BXM * MO + MO && tid < BXM * MO + MO + BXM) {
+            const int rr = tid - BXM * MO - MO;
+            const int xx = x0 + rr;
+            T v = T(0);
+            if (xx < n1) {
+                const int64_t mm = mem((int64_t)line * n1 + xx);
+                v = in[mm];
+                if (scale) v *= scale[mm];
+            }
+            s_rhs[rr] = v;
+        }
         // wait: own line up to x0, and the two lines that cover the others
-        if (tid == 0) {
+        // (the three counters read together, one round trip per poll)
+        if (tid == BXM * MO + MO + BXM) {
             const unsigned needo = (unsigned)min(n1, x0 + BXM + a.Hx);
-            if (x0 > 0) {
-                while (ld_coh(&prog[line]) < (unsigned)x0) __builtin_amdgcn_s_sleep(1);
-            }
-            if (iy > 0) {
-                while (ld_coh(&prog[line - 1]) < needo) __builtin_amdgcn_s_sleep(1);
-            }
-            if (iz > 0) {
-                const int l2 = (iz - 1) * n1 + min(iy + a.Hy, n1 - 1);
-                while (ld_coh(&prog[l2]) < needo) __builtin_amdgcn_s_sleep(1);
+            const int l2 = iz > 0 ? (iz - 1) * n1 + min(iy + a.Hy, n1 - 1) : line;
+            for (;;) {
+                const unsigned v0 = x0 > 0 ? ld_coh(&prog[line]) : ~0u;
+                const unsigned v1 = iy > 0 ? ld_coh(&prog[line - 1]) : ~0u;
+                const unsigned v2 = iz > 0 ? ld_coh(&prog[l2]) : ~0u;
+                if (v0 >= (unsigned)x0 && v1 >= needo && v2 >= needo) break;
+                __builtin_amdgcn_s_sleep(1);
             }
         }
         __syncthreads();
@@ -667,33 +689,13 @@ __global__ __launch_bounds__(NT) void sweep3d_kernel(S3Args<T> a) {
         T acc = terms(false);
         if (__builtin_expect(isnan(acc), 0)) acc = terms(true);
         s_part[grp][r] = acc;
-        // in-line coefficients and the values of the preceding rows
-        if (tid < BXM * MO) {
-            const int rr = tid / MO, m = tid % MO;   // coefficient of (-(m+1), 0, 0) for row rr
-            const int k = a.own[m];
-            const int xx = x0 + rr;
-            T c = T(0);
-            if (k >= 0 && xx < n1 && xx - (m + 1) >= 0) {
-                const int64_t ipr = (int64_t)line * n1 + xx;
-                c = A[(int64_t)k * a.ldo + (REV ? mem(ipr - (m + 1)) : mem(ipr))];
-            }
-            s_coef[rr][m] = c;
-        } else if (tid < BXM * MO + MO) {
+        // the values of the preceding rows of the line (final after the wait)
+        if (tid >= BXM * MO && tid < BXM * MO + MO) {
             const int m = tid - BXM * MO;       // row x0 - MO + m
             const int xx = x0 - MO + m;
             T v = T(0);
             if (xx >= 0) v = ld_coh(&out[mem((int64_t)line * n1 + xx)]);
             s_prev[m] = v;
-        } else if (tid < BXM * MO + MO + BXM) {
-            const int rr = tid - BXM * MO - MO;
-            const int xx = x0 + rr;
-            T v = T(0);
-            if (xx < n1) {
-                const int64_t mm = mem((int64_t)line * n1 + xx);
-                v = in[mm];
-                if (scale) v *= scale[mm];
-            }
-            s_rhs[rr] = v;
         }
         __syncthreads();
         if (tid < BXM) {
