@@ -361,3 +361,29 @@ def test_3d_fp32_only_factor():
         assert i2["relres_true"] <= 1e-10
     x, info = pcg_solve(P, M_only, Fg, rtol=1e-10, raise_on_error=False)
     assert info["status"] == "LGP_E_UNSUPPORTED"
+
+
+@pytest.mark.parametrize("d,N,T,ring_planes", [(3, 16, 4, 10), (3, 18, 6, 0), (2, 40, 8, 0)])
+def test_factor_bitwise_repeatable(d, N, T, ring_planes, monkeypatch):
+    """The factorisation gives the same bits on every run: a step whose
+    neighbour row is not yet written is formed again with the operations of
+    the first attempt, in the same order, so which steps waited (a matter of
+    timing) does not show in L or D (3D through six window launches, 3D with
+    4-row chunks, 2D)."""
+    from paper_2004_13961_amd.solver import Factor, Problem
+    from paper_2004_13961_amd.workload import family_nodal
+    print("case repeatable d=%d N=%d T=%d ring_planes=%d" % (d, N, T, ring_planes), flush=True)
+    if ring_planes:
+        monkeypatch.setenv("LGP_RING_PLANES", str(ring_planes))
+    a_g, b_g, _, _ = family_nodal(d, N, 6, 4, with_rhs=False)
+    P = Problem(d, N, _dev(a_g).reshape(-1), _dev(b_g).reshape(-1))
+    runs = []
+    for rep in range(3):
+        M = Factor(P, T, T)
+        desc = M.describe()
+        runs.append((desc["L"].clone(), desc["D"].clone(), desc["factor_kernel"]))
+        del M, desc
+    torch.cuda.synchronize()
+    assert runs[0][2] == (3 if d == 3 else 2)
+    for L, D, _ in runs[1:]:
+        assert torch.equal(L, runs[0][0]) and torch.equal(D, runs[0][1])
