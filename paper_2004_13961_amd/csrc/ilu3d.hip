@@ -38,9 +38,9 @@
 // offsets j are taken grid line by grid line, the line taken longest ago
 // first and the row's own line last, x ascending within a line, so
 // consecutive steps read x-neighbouring rows of the window (a quarter less
-// traffic beyond the L2 than an order by hyperplane level). The row's u vector sits in
-// LDS at the same box positions, so p(d_k) = p(d_l) + p(d_j) - P0, and a
-// pair is named by p(d_l) alone. Pairs at adjacent positions p, p + 1 form a
+// traffic beyond the L2 than an order by hyperplane level). The row's u
+// vector sits in LDS at the same box positions, so p(d_k) = p(d_l) + p(d_j)
+// - P0, and a pair is named by p(d_l) alone. Pairs at adjacent positions p, p + 1 form a
 // duo, which one 16-byte load gathers and one LDS read pairs with u (a pair
 // without a neighbour is a duo with a flagged, zeroed second term); a duo is
 // the 16-bit value 8 p | flag, two per 32-bit word. The duos of all steps
@@ -81,19 +81,17 @@ static ChunkKeys chunk_keys(int B, int Hx, int Hy, int Hz) {
     return k;
 }
 
-// waves per workgroup of the 3D factor kernel: each wave holds its row's
-// u vector (n_lower + 2 doubles) in LDS
-// pairs per lane in one packet of the 3D factor kernel
 constexpr int kRowsPerPacket = 2;   // rows of 64 duo words in a packet of the 3D factor kernel
 
 // The chunked kernel lays out each row's u vector (LDS) and the rows of the
 // window by position in the lower half of the stencil's bounding box,
 // p(delta) = P0 + dz XY + dy X + dx (X = 2 Hx + 1, XY = X (2 Hy + 1), P0 the
-// diagonal), so a pair of the recurrence is one 16-bit byte offset: the
-// neighbour row's entry p(delta_l) and u at p(delta_l) + (p(delta_j) - P0).
+// diagonal), so a pair of the recurrence is named by one 16-bit byte offset:
+// the neighbour row's entry p(delta_l) and u at p(delta_l) + (p(delta_j) - P0).
 // This needs the box order (z, y, x) to be the order of the columns, i.e. a
 // grid wider than twice the reach in x and y; other grids take the generic
-// kernel. Returns the rows per chunk (0: generic kernel).
+// kernel. Returns the rows per chunk (0: generic kernel): a power of two up
+// to 8 whose u vectors (P0 + 2 doubles each) fit 150 KB of LDS.
 static int factor3_waves(const Factor& F) {
     if (F.n1 <= 2 * std::max(F.Hx, F.Hy) || F.bPD + 1 > 8191) return 0;
     const size_t per = (size_t)(F.bP0 + 2) * 8;
@@ -161,11 +159,11 @@ size_t plan_factor3(Factor& F, void* buf, int store) {
     F.steps = c.take<int>((size_t)4 * (nlo + 1));
     F.sdxyz = c.take<int>(nlo + 1);
     F.pairw = c.take<unsigned>((size_t)F.npairs + 64 * 8);
-    // pairs of the chunked kernel: two 16-bit positions per word, each step
-    // padded to a multiple of 128 pairs, then 64 Q zero words
+    // duo words of the chunked kernel: two 16-bit duos per word, each step
+    // padded to rows of 64 words, then one packet of zero words
     F.pw16 = c.take<unsigned>(F.fB > 0 ? ((size_t)F.npairs + 128 * (size_t)(nlo + 1)) / 2 + 64 * kRowsPerPacket : 1);
     F.kofp = c.take<int>(F.fB > 0 ? (size_t)F.bP0 : 1);
-    // packets: at most one per 64 pairs of each step, plus one per step
+    // packets: fewer than one per 128 pairs of each step, plus one per step
     F.pk = c.take<int>((size_t)4 * ((size_t)F.npairs / 128 + 2 * (size_t)nlo + 2));
     F.chunk_order = c.take<int>(F.nchunks > 0 ? F.nchunks : 1);
     F.blk_order = c.take<int>((size_t)F.nlines * F.snxb);
@@ -221,7 +219,7 @@ struct F3Args {
     int64_t n, ring_rows, ldo;
     int ring_planes;
     int tk_begin, tk_end;
-    const int4* pk;          // packets {first pair, count, packed (dx,dy,dz), j | first << 30 | last << 31}
+    const int4* pk;          // packets {first word, rows, packed (dx,dy,dz), j | first << 30 | last << 31}
     const int2* jrange;      // [nlo] word range of the step of offset j
     const int4* offs;        // [nlo + 1] (dx, dy, dz, linear) in column order
     const unsigned* pairw;   // duo words: two duos (byte offset 8 p | one-pair flag), low half first
